@@ -1,0 +1,216 @@
+"""Plain, slow, float64 CPU oracle for the Green Function Convolution (GFC) solve.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import or call this module;
+only tests, the smoke check and the benchmark's CPU-baseline leg use it. It shares no code
+with the HIP path and reads nothing the HIP path writes.
+
+What it computes (block-centred convention of Algorithm A/B):
+
+* The torus is Z_M x Z_N. An H x W gradient field (gx, gy) is embedded at offset
+  (oy, ox) = (floor((M-H)/2), floor((N-W)/2)) in zeros (the padding of Sec. 2.3.2).
+* L = div E with backward differences on the torus (eq. (3)):
+      L[y,x] = Ex[y,x] - Ex[y,x-1] + Ey[y,x] - Ey[y-1,x]          (indices mod M, N)
+* Green's spectrum (eqs. (19)-(22), Algorithm A): G^ = F(dirac) / F(laplace) with the
+  Dirac at [1,1] and the 5-point kernel at [0:3,0:3]; this equals 1/lambda with
+      lambda(k,l) = -4 sin^2(pi k/M) - 4 sin^2(pi l/N).
+  Readings taken where the paper is silent or inconsistent:
+    - stencil sign: Algorithm A's +Laplacian ([[0,1,0],[1,-4,1],[0,1,0]]), the sign for
+      which L = div E reconstructs +I; eq. (15) prints the negated kernel;
+    - DC bin: lambda(0,0) = 0 makes Algorithm A divide by zero; G^(0,0) := 0 (the
+      pseudo-inverse). The result does not depend on it: sum(L) = 0 exactly on the torus.
+* v = R(F^-1(F(L) o G^)) (eq. (23)); u = v[block] - v[0,0] (Algorithm B's constant and
+  crop; v[0,0] lies in the zero padding, Sec. 2.3.2's choice of c).
+* Backward (adjoint of the linear map (gx, gy) -> u):
+      r = embed(du) - sum(du) * delta_(0,0),  w = g (*) r  (g is real and even),
+      dgx = -(w[y,x+1] - w[y,x]),  dgy = -(w[y+1,x] - w[y,x])   on the block.
+
+Three independent forward implementations are given so they can check one another:
+`solve_fft` (numpy/scipy FFT, the reference for GPU parity), `solve_direct` (explicit DFT
+matrices and a literal circular convolution, tiny grids only) and `lstsq_torus` (dense least
+squares of the torus gradient system, the optimality statement of Sec. 2.2, tiny grids).
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import scipy.fft as sfft
+
+__all__ = [
+    "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_algorithm_a",
+    "embed", "divergence", "solve_fft", "solve_direct", "lstsq_torus", "torus_gradient",
+    "solve_backward", "green_function", "cpu_workers",
+]
+
+
+def cpu_workers() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def block_offset(H: int, W: int, M: int, N: int) -> tuple[int, int]:
+    """Offset of the image block in the torus: centred, floor((M-H)/2), floor((N-W)/2)."""
+    if M < H + 2 or N < W + 2:
+        raise ValueError("torus must exceed the image by at least 2 in each direction")
+    return (M - H) // 2, (N - W) // 2
+
+
+def laplacian_symbol(M: int, N: int) -> np.ndarray:
+    """lambda(k,l) of the +5-point Laplacian on Z_M x Z_N, shape [M, N], float64."""
+    k = np.arange(M, dtype=np.float64)
+    l = np.arange(N, dtype=np.float64)
+    a = -4.0 * np.sin(np.pi * k / M) ** 2
+    b = -4.0 * np.sin(np.pi * l / N) ** 2
+    return a[:, None] + b[None, :]
+
+
+def green_spectrum(M: int, N: int) -> np.ndarray:
+    """Numerical Green's spectrum G^ = 1/lambda, G^(0,0) = 0 (eq. (22) in closed form)."""
+    lam = laplacian_symbol(M, N)
+    G = np.zeros_like(lam)
+    nz = lam != 0.0
+    G[nz] = 1.0 / lam[nz]
+    return G
+
+
+def green_spectrum_algorithm_a(M: int, N: int, dirac_pos=(1, 1), kernel=None) -> np.ndarray:
+    """Algorithm A as printed: fft2 of the Dirac over fft2 of the zero-padded Laplace kernel.
+
+    `kernel` is the 3x3 stencil placed at [0:3, 0:3] (Algorithm A's by default). The DC bin,
+    which Algorithm A leaves as 1/0, is set to 0. Returns the complex spectrum.
+    """
+    if kernel is None:
+        kernel = np.array([[0.0, 1.0, 0.0], [1.0, -4.0, 1.0], [0.0, 1.0, 0.0]])
+    dirac = np.zeros((M, N))
+    dirac[dirac_pos] = 1.0
+    lap = np.zeros((M, N))
+    lap[0:3, 0:3] = kernel
+    num = np.fft.fft2(dirac)
+    den = np.fft.fft2(lap)
+    out = np.zeros((M, N), dtype=np.complex128)
+    nz = np.abs(den) > 1e-300
+    out[nz] = num[nz] / den[nz]
+    return out
+
+
+def green_function(M: int, N: int) -> np.ndarray:
+    """Spatial Green's function g = F^-1(G^) (real, even), shape [M, N]."""
+    return np.real(np.fft.ifft2(green_spectrum(M, N)))
+
+
+def embed(a: np.ndarray, M: int, N: int, oy: int, ox: int) -> np.ndarray:
+    """Zero-padded copy of a [..., H, W] array at offset (oy, ox) of an [..., M, N] torus."""
+    a = np.asarray(a, dtype=np.float64)
+    H, W = a.shape[-2:]
+    out = np.zeros(a.shape[:-2] + (M, N), dtype=np.float64)
+    out[..., oy:oy + H, ox:ox + W] = a
+    return out
+
+
+def divergence(gx, gy, M: int, N: int, oy: int, ox: int) -> np.ndarray:
+    """L = div E of the embedded field with backward differences on the torus (eq. (3))."""
+    Ex = embed(gx, M, N, oy, ox)
+    Ey = embed(gy, M, N, oy, ox)
+    return (Ex - np.roll(Ex, 1, axis=-1)) + (Ey - np.roll(Ey, 1, axis=-2))
+
+
+def _as_batch(a):
+    a = np.asarray(a, dtype=np.float64)
+    return (a[None], True) if a.ndim == 2 else (a, False)
+
+
+def solve_fft(gx, gy, M: int, N: int, workers: int | None = None) -> np.ndarray:
+    """Forward GFC solve in float64 via library FFTs: eq. (23) and Algorithm B.
+
+    gx, gy: [H, W] or [B, H, W] (float32 inputs are promoted exactly). Returns u like gx.
+    """
+    gx, single = _as_batch(gx)
+    gy, _ = _as_batch(gy)
+    B, H, W = gx.shape
+    oy, ox = block_offset(H, W, M, N)
+    Gh = green_spectrum(M, N)[:, : N // 2 + 1]
+    w = workers if workers is not None else cpu_workers()
+    out = np.empty((B, H, W), dtype=np.float64)
+    for b in range(B):
+        L = divergence(gx[b], gy[b], M, N, oy, ox)
+        v = sfft.irfft2(sfft.rfft2(L, workers=w) * Gh, s=(M, N), workers=w)
+        out[b] = v[oy:oy + H, ox:ox + W] - v[0, 0]
+    return out[0] if single else out
+
+
+def _dft_matrix(n: int, sign: float) -> np.ndarray:
+    j = np.arange(n)
+    return np.exp(sign * 2j * np.pi * np.outer(j, j) / n)
+
+
+def solve_direct(gx, gy, M: int, N: int) -> np.ndarray:
+    """Forward solve with no FFT: g from explicit inverse-DFT matrices applied to the closed
+    form G^, then a literal circular convolution of L over its support (eq. (4)).
+    Cost O(M N (H+1) (W+1)); intended for grids of at most ~128 x 128."""
+    gx, single = _as_batch(gx)
+    gy, _ = _as_batch(gy)
+    B, H, W = gx.shape
+    oy, ox = block_offset(H, W, M, N)
+    Fm = _dft_matrix(M, +1.0)
+    Fn = _dft_matrix(N, +1.0)
+    g = np.real(Fm @ green_spectrum(M, N) @ Fn.T) / (M * N)
+    out = np.empty((B, H, W))
+    yy = np.arange(M)[:, None]
+    xx = np.arange(N)[None, :]
+    for b in range(B):
+        L = divergence(gx[b], gy[b], M, N, oy, ox)
+        v = np.zeros((M, N))
+        for qy, qx in zip(*np.nonzero(L)):
+            v += L[qy, qx] * g[(yy - qy) % M, (xx - qx) % N]
+        out[b] = v[oy:oy + H, ox:ox + W] - v[0, 0]
+    return out[0] if single else out
+
+
+def torus_gradient(M: int, N: int) -> np.ndarray:
+    """Dense forward-difference gradient matrix D (2MN x MN) on Z_M x Z_N; rows [Dx; Dy]."""
+    n = M * N
+    idx = np.arange(n).reshape(M, N)
+    D = np.zeros((2 * n, n))
+    r = np.arange(n)
+    D[r, idx.ravel()] -= 1.0
+    D[r, np.roll(idx, -1, axis=1).ravel()] += 1.0
+    D[n + r, idx.ravel()] -= 1.0
+    D[n + r, np.roll(idx, -1, axis=0).ravel()] += 1.0
+    return D
+
+
+def lstsq_torus(gx, gy, M: int, N: int) -> np.ndarray:
+    """argmin_v ||D v - E||^2 on the torus by dense least squares (the optimality statement
+    of Sec. 2.2, eqs. (8)-(14)), then Algorithm B's constant and crop. Tiny grids only."""
+    gx = np.asarray(gx, dtype=np.float64)
+    gy = np.asarray(gy, dtype=np.float64)
+    H, W = gx.shape
+    oy, ox = block_offset(H, W, M, N)
+    E = np.concatenate([embed(gx, M, N, oy, ox).ravel(), embed(gy, M, N, oy, ox).ravel()])
+    v, *_ = np.linalg.lstsq(torus_gradient(M, N), E, rcond=None)
+    v = v.reshape(M, N)
+    return v[oy:oy + H, ox:ox + W] - v[0, 0]
+
+
+def solve_backward(du, M: int, N: int, workers: int | None = None):
+    """Adjoint of the forward solve: returns (dgx, dgy) with the shape of du."""
+    du, single = _as_batch(du)
+    B, H, W = du.shape
+    oy, ox = block_offset(H, W, M, N)
+    Gh = green_spectrum(M, N)[:, : N // 2 + 1]
+    wk = workers if workers is not None else cpu_workers()
+    dgx = np.empty((B, H, W))
+    dgy = np.empty((B, H, W))
+    for b in range(B):
+        r = embed(du[b], M, N, oy, ox)
+        r[0, 0] -= du[b].sum()
+        w = sfft.irfft2(sfft.rfft2(r, workers=wk) * Gh, s=(M, N), workers=wk)
+        gxf = -(np.roll(w, -1, axis=1) - w)
+        gyf = -(np.roll(w, -1, axis=0) - w)
+        dgx[b] = gxf[oy:oy + H, ox:ox + W]
+        dgy[b] = gyf[oy:oy + H, ox:ox + W]
+    if single:
+        return dgx[0], dgy[0]
+    return dgx, dgy

@@ -1,0 +1,362 @@
+"""Pins for the float64 oracle: each test ties it to something other than itself.
+
+The paper prints no worked numeric example, so the pins are the paper's printed kernels
+(tests/golden/paper_kernels.json), a hand-derived 4x4 spectrum (tests/golden/green_4x4_hand.json),
+identities the paper states (eqs. (4), (8)-(14), (16), (22), (23)), brute force on tiny grids
+and closed-form asymptotics (eq. (5)). Three forward implementations of different construction
+(library FFT, explicit DFT matrices plus literal convolution, dense least squares) must agree.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gfc_synth as synth
+import oracle as O
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _load(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+def _rand_field(rng, H, W):
+    return rng.normal(size=(H, W)), rng.normal(size=(H, W))
+
+
+def _framed_conservative(rng, H, W):
+    """Image with zero first row and first column (padding taken before the gradient,
+    Sec. 2.3.2) and its forward-difference gradient with zero exterior."""
+    S = synth.gaussian_sum_field(rng, H, W) + 0.1 * rng.normal(size=(H, W))
+    S[0, :] = 0.0
+    S[:, 0] = 0.0
+    gx, gy = synth.forward_gradient(S)
+    return S, gx, gy
+
+
+# ---------------------------------------------------------------- Green's spectrum (A0)
+
+@pytest.mark.parametrize("M,N", [(12, 10), (16, 16), (9, 14), (30, 24)])
+def test_closed_form_equals_algorithm_a_with_printed_kernel(golden_dir, M, N):
+    k = _load(golden_dir, "paper_kernels.json")
+    lap = np.array(k["algorithm_a_laplace"]["value"], dtype=float)
+    pos = tuple(k["algorithm_a_dirac_position"]["value"])
+    Ga = O.green_spectrum_algorithm_a(M, N, dirac_pos=pos, kernel=lap)
+    Gc = O.green_spectrum(M, N)
+    mask = np.ones((M, N), bool)
+    mask[0, 0] = False
+    assert np.max(np.abs(Ga.imag[mask])) < 1e-12
+    rel = np.abs(Ga.real[mask] - Gc[mask]) / np.abs(Gc[mask])
+    assert rel.max() < 1e-12
+    # Algorithm A's literal division is 1/0 at DC: the oracle's DC reading is 0.
+    assert Gc[0, 0] == 0.0
+
+
+def test_green_4x4_hand_derived(golden_dir):
+    g = _load(golden_dir, "green_4x4_hand.json")
+    expect = np.array([[n / d for n, d in row] for row in g["G_hat_numerator_over_denominator"]])
+    assert np.allclose(O.green_spectrum(4, 4), expect, rtol=0, atol=1e-15)
+    n, d = g["g00_num_den"]
+    assert abs(O.green_function(4, 4)[0, 0] - n / d) < 1e-15
+
+
+@pytest.mark.parametrize("M,N", [(6, 8), (7, 5)])
+def test_green_function_is_pseudo_inverse_of_dense_laplacian(M, N):
+    """Brute force: g = pinv(Laplacian matrix) applied to a Dirac (no FFT involved)."""
+    D = O.torus_gradient(M, N)
+    lap = -(D.T @ D)  # +5-point Laplacian as a dense MN x MN matrix
+    e0 = np.zeros(M * N)
+    e0[0] = 1.0
+    g_brute = (np.linalg.pinv(lap) @ e0).reshape(M, N)
+    assert np.max(np.abs(O.green_function(M, N) - g_brute)) < 1e-12
+
+
+def test_discrete_green_identity_eq16():
+    """K (*) g = delta - 1/(MN): eq. (16) on the torus with the DC projection."""
+    M, N = 64, 48
+    g = O.green_function(M, N)
+    lap_g = (np.roll(g, 1, 0) + np.roll(g, -1, 0) + np.roll(g, 1, 1) + np.roll(g, -1, 1) - 4 * g)
+    target = -np.full((M, N), 1.0 / (M * N))
+    target[0, 0] += 1.0
+    assert np.max(np.abs(lap_g - target)) < 1e-12
+    assert np.max(np.abs(g - g[(-np.arange(M)) % M][:, (-np.arange(N)) % N])) < 1e-14  # even
+
+
+def test_far_field_matches_eq5_logarithm(golden_dir):
+    """Away from the source, g behaves like ln(r)/S_1 (eq. (5)-(6), n = 2), with the sign that
+    goes with Algorithm A's +Laplacian (reading of the stencil sign)."""
+    s2 = _load(golden_dir, "paper_kernels.json")["eq6_surface_2d"]["value"]
+    assert abs(s2 - 2 * math.pi) < 1e-15
+    g = O.green_function(512, 512)
+    for r1, r2 in [(10, 20), (16, 64), (8, 40)]:
+        d_num = g[r1, 0] - g[r2, 0]
+        d_cont = math.log(r1 / r2) / s2
+        assert abs(d_num - d_cont) < 5e-3
+
+
+# ---------------------------------------------------------------- forward solve (A1-A7)
+
+def test_three_independent_forward_solvers_agree():
+    rng = np.random.default_rng(7)
+    H, W, M, N = 5, 6, 12, 14
+    gx, gy = _rand_field(rng, H, W)
+    u_fft = O.solve_fft(gx, gy, M, N)
+    u_dir = O.solve_direct(gx, gy, M, N)
+    u_ls = O.lstsq_torus(gx, gy, M, N)
+    assert np.max(np.abs(u_fft - u_dir)) < 1e-12
+    assert np.max(np.abs(u_fft - u_ls)) < 1e-11
+
+
+def test_direct_equals_fft_on_the_small_workload():
+    w = synth.make_workload("small64")
+    u_fft = O.solve_fft(w.gx, w.gy, w.M, w.N)
+    u_dir = O.solve_direct(w.gx[0], w.gy[0], w.M, w.N)
+    assert np.max(np.abs(u_fft[0] - u_dir)) < 1e-10 * np.max(np.abs(u_fft))
+
+
+@pytest.mark.parametrize("H,W,M,N", [(6, 7, 14, 16), (20, 31, 40, 64), (64, 64, 128, 128)])
+def test_framed_conservative_field_reconstructs_exactly(H, W, M, N):
+    """A conservative field taken after zero padding reconstructs its image exactly, offset
+    included because the reference pixel lies in the padding (Sec. 2.3.2, eq. (23))."""
+    rng = np.random.default_rng(H * 1000 + W)
+    S, gx, gy = _framed_conservative(rng, H, W)
+    u = O.solve_fft(gx, gy, M, N)
+    assert np.max(np.abs(u - S)) < 1e-12
+    if M * N <= 14 * 16:
+        assert np.max(np.abs(O.solve_direct(gx, gy, M, N) - S)) < 1e-12
+
+
+def test_unframed_field_misses_boundary_flux():
+    """Negative control: without the zero frame the left/top boundary fluxes are absent from
+    H x W difference arrays and the reconstruction is off by O(1)."""
+    rng = np.random.default_rng(3)
+    S = synth.gaussian_sum_field(rng, 6, 7) + 0.5
+    gx, gy = synth.forward_gradient(S)
+    u = O.solve_fft(gx, gy, 14, 16)
+    assert np.max(np.abs(u - S)) > 0.1
+
+
+def test_eq15_sign_reconstructs_the_negative_image(golden_dir):
+    """Reading of the stencil sign: with eq. (15)'s kernel the solve returns -I."""
+    k = _load(golden_dir, "paper_kernels.json")
+    lap15 = np.array(k["eq15_laplace"]["value"], dtype=float)
+    H, W, M, N = 6, 7, 14, 16
+    rng = np.random.default_rng(11)
+    S, gx, gy = _framed_conservative(rng, H, W)
+    G15 = O.green_spectrum_algorithm_a(M, N, kernel=lap15)
+    oy, ox = O.block_offset(H, W, M, N)
+    L = O.divergence(gx, gy, M, N, oy, ox)
+    v = np.real(np.fft.ifft2(np.fft.fft2(L) * G15))
+    u15 = v[oy:oy + H, ox:ox + W] - v[0, 0]
+    assert np.max(np.abs(u15 + S)) < 1e-12
+
+
+def test_gfc_equals_dense_torus_least_squares():
+    """Sec. 2.2: the GFC output is the least-squares potential of the padded torus field."""
+    rng = np.random.default_rng(5)
+    for H, W, M, N in [(4, 5, 8, 10), (6, 6, 12, 12)]:
+        gx, gy = _rand_field(rng, H, W)
+        assert np.max(np.abs(O.solve_fft(gx, gy, M, N) - O.lstsq_torus(gx, gy, M, N))) < 1e-11
+
+
+def test_least_error_against_other_reconstructions():
+    """Hilbert projection (eqs. (8)-(14)): no other potential has a smaller torus gradient
+    error than GFC's. Checked against random perturbations and a Neumann least-squares solve
+    restricted to the image (a Perez-style solution) embedded in the torus."""
+    rng = np.random.default_rng(9)
+    H, W, M, N = 6, 7, 14, 16
+    gx, gy = _rand_field(rng, H, W)
+    oy, ox = O.block_offset(H, W, M, N)
+    D = O.torus_gradient(M, N)
+    E = np.concatenate([O.embed(gx, M, N, oy, ox).ravel(), O.embed(gy, M, N, oy, ox).ravel()])
+    u = O.solve_fft(gx, gy, M, N)
+    # rebuild the full-torus GFC potential from the definition (eq. (23))
+    v = np.real(np.fft.ifft2(np.fft.fft2(O.divergence(gx, gy, M, N, oy, ox)) * O.green_spectrum(M, N)))
+    err = np.linalg.norm(D @ v.ravel() - E)
+    for _ in range(20):
+        d = rng.normal(size=(M, N))
+        assert np.linalg.norm(D @ (v + 1e-3 * d).ravel() - E) > err
+    # Neumann LS on the image only (interior edges), embedded with zero outside, best constant
+    nx = np.zeros((H * (W - 1), H * W))
+    ny = np.zeros(((H - 1) * W, H * W))
+    idx = np.arange(H * W).reshape(H, W)
+    r = 0
+    for y in range(H):
+        for x in range(W - 1):
+            nx[r, idx[y, x]] = -1
+            nx[r, idx[y, x + 1]] = 1
+            r += 1
+    r = 0
+    for y in range(H - 1):
+        for x in range(W):
+            ny[r, idx[y, x]] = -1
+            ny[r, idx[y + 1, x]] = 1
+            r += 1
+    A = np.vstack([nx, ny])
+    rhs = np.concatenate([gx[:, :-1].ravel(), gy[:-1, :].ravel()])
+    p, *_ = np.linalg.lstsq(A, rhs, rcond=None)
+    best = np.inf
+    for c in np.linspace(-5, 5, 201):
+        vv = O.embed(p.reshape(H, W) + c, M, N, oy, ox)
+        best = min(best, np.linalg.norm(D @ vv.ravel() - E))
+    assert err < best
+    # and GFC's own crop is the image part of that optimum up to the constant
+    assert np.max(np.abs(u - (v[oy:oy + H, ox:ox + W] - v[0, 0]))) < 1e-13
+
+
+def test_interior_laplacian_of_output_equals_input_laplacian():
+    rng = np.random.default_rng(13)
+    H, W, M, N = 40, 50, 96, 100
+    gx, gy = _rand_field(rng, H, W)
+    u = O.solve_fft(gx, gy, M, N)
+    oy, ox = O.block_offset(H, W, M, N)
+    L = O.divergence(gx, gy, M, N, oy, ox)[oy:oy + H, ox:ox + W]
+    lap = u[2:, 1:-1] + u[:-2, 1:-1] + u[1:-1, 2:] + u[1:-1, :-2] - 4 * u[1:-1, 1:-1]
+    assert np.max(np.abs(lap - L[1:-1, 1:-1])) < 1e-12
+
+
+def test_linearity_and_translation_equivariance():
+    rng = np.random.default_rng(17)
+    H, W, M, N = 10, 12, 24, 30
+    a = _rand_field(rng, H, W)
+    b = _rand_field(rng, H, W)
+    ua = O.solve_fft(*a, M, N)
+    ub = O.solve_fft(*b, M, N)
+    uab = O.solve_fft(2.0 * a[0] - 0.5 * b[0], 2.0 * a[1] - 0.5 * b[1], M, N)
+    assert np.max(np.abs(uab - (2.0 * ua - 0.5 * ub))) < 1e-12
+    # another block position changes u only by a constant (torus translation equivariance)
+    oy, ox = O.block_offset(H, W, M, N)
+    G = O.green_spectrum(M, N)
+    for (py, px) in [(0, 0), (3, 17), (M - H, N - W)]:
+        L = O.divergence(*a, M, N, py, px)
+        v = np.real(np.fft.ifft2(np.fft.fft2(L) * G))
+        d = v[py:py + H, px:px + W] - ua
+        assert np.ptp(d) < 1e-12
+        # with the reference pixel moved along with the block, u is identical
+        ref = v[(py - oy) % M, (px - ox) % N]
+        assert np.max(np.abs(v[py:py + H, px:px + W] - ref - ua)) < 1e-12
+
+
+def test_dc_bin_value_is_irrelevant():
+    rng = np.random.default_rng(19)
+    H, W, M, N = 8, 9, 20, 22
+    gx, gy = _rand_field(rng, H, W)
+    oy, ox = O.block_offset(H, W, M, N)
+    L = O.divergence(gx, gy, M, N, oy, ox)
+    assert abs(L.sum()) < 1e-12
+    G = O.green_spectrum(M, N)
+    G2 = G.copy()
+    G2[0, 0] = 123.0
+    v1 = np.fft.ifft2(np.fft.fft2(L) * G)
+    v2 = np.fft.ifft2(np.fft.fft2(L) * G2)
+    u1 = np.real(v1)[oy:oy + H, ox:ox + W] - np.real(v1)[0, 0]
+    u2 = np.real(v2)[oy:oy + H, ox:ox + W] - np.real(v2)[0, 0]
+    assert np.max(np.abs(u1 - u2)) < 1e-12
+    # eq. (23)'s real part: the imaginary residue is rounding only
+    assert np.max(np.abs(v1.imag)) < 1e-13 * np.max(np.abs(v1.real))
+
+
+# ---------------------------------------------------------------- backward (A8)
+
+def test_adjoint_dot_product():
+    rng = np.random.default_rng(23)
+    for H, W, M, N in [(7, 9, 16, 20), (32, 32, 64, 64), (31, 17, 64, 36)]:
+        gx, gy = _rand_field(rng, H, W)
+        du = rng.normal(size=(H, W))
+        u = O.solve_fft(gx, gy, M, N)
+        dgx, dgy = O.solve_backward(du, M, N)
+        lhs = np.sum(u * du)
+        rhs = np.sum(gx * dgx) + np.sum(gy * dgy)
+        assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_backward_matches_central_finite_differences():
+    """Differentiable layer on the 2x1x32x32 / 64x64 instance: loss = mean((u - t)^2),
+    gradient from the adjoint vs float64 central differences with h = 1e-6."""
+    w = synth.make_workload("layer256", B=2, C=1, H=32, W=32, rect=8, grid=(64, 64))
+    gx = w.gx.astype(np.float64)
+    gy = w.gy.astype(np.float64)
+    t = w.extra["target"].astype(np.float64)
+    M, N = w.M, w.N
+    n = gx.size
+
+    def loss(ax, ay):
+        return np.sum((O.solve_fft(ax, ay, M, N) - t) ** 2) / n
+
+    u = O.solve_fft(gx, gy, M, N)
+    dgx, dgy = O.solve_backward(2.0 * (u - t) / n, M, N)
+    rng = np.random.default_rng(29)
+    h = 1e-6
+    for _ in range(40):
+        b, y, x = rng.integers(0, 2), rng.integers(0, 32), rng.integers(0, 32)
+        for arr, grad in ((gx, dgx), (gy, dgy)):
+            p = arr.copy()
+            m = arr.copy()
+            p[b, y, x] += h
+            m[b, y, x] -= h
+            fd = (loss(p, gy) - loss(m, gy)) / (2 * h) if arr is gx else (loss(gx, p) - loss(gx, m)) / (2 * h)
+            assert abs(fd - grad[b, y, x]) < 1e-8 + 1e-5 * abs(grad[b, y, x])
+
+
+def test_backward_reference_term_is_required():
+    """Dropping the -sum(du) delta term of the adjoint breaks the dot-product identity."""
+    rng = np.random.default_rng(31)
+    H, W, M, N = 7, 9, 16, 20
+    gx, gy = _rand_field(rng, H, W)
+    du = rng.normal(size=(H, W)) + 1.0
+    u = O.solve_fft(gx, gy, M, N)
+    oy, ox = O.block_offset(H, W, M, N)
+    r = O.embed(du, M, N, oy, ox)  # no delta term
+    w = np.real(np.fft.ifft2(np.fft.fft2(r) * O.green_spectrum(M, N)))
+    bx = -(np.roll(w, -1, 1) - w)[oy:oy + H, ox:ox + W]
+    by = -(np.roll(w, -1, 0) - w)[oy:oy + H, ox:ox + W]
+    assert abs(np.sum(u * du) - (np.sum(gx * bx) + np.sum(gy * by))) > 1e-6
+
+
+# ---------------------------------------------------------------- pin sensitivity
+
+@pytest.mark.parametrize("mutation", ["forward_difference_div", "drop_y_term", "transpose_grid",
+                                      "reference_pixel", "stencil_sign"])
+def test_planted_oracle_mistakes_are_caught(monkeypatch, mutation):
+    """Plant a plausible mistake in the oracle (on the CPU) and check a pin fails."""
+    import oracle.gfc_oracle as G
+    real_div = G.divergence
+    real_green = G.green_spectrum
+
+    if mutation == "forward_difference_div":
+        def bad(gx, gy, M, N, oy, ox):
+            Ex, Ey = G.embed(gx, M, N, oy, ox), G.embed(gy, M, N, oy, ox)
+            return (np.roll(Ex, -1, -1) - Ex) + (np.roll(Ey, -1, -2) - Ey)
+        monkeypatch.setattr(G, "divergence", bad)
+    elif mutation == "drop_y_term":
+        def bad(gx, gy, M, N, oy, ox):
+            Ex = G.embed(gx, M, N, oy, ox)
+            return Ex - np.roll(Ex, 1, -1)
+        monkeypatch.setattr(G, "divergence", bad)
+    elif mutation == "transpose_grid":
+        def bad(M, N):  # the two axis lengths swapped inside the symbol
+            k = np.arange(M)[:, None]
+            l = np.arange(N)[None, :]
+            lam = -4 * np.sin(np.pi * k / N) ** 2 - 4 * np.sin(np.pi * l / M) ** 2
+            out = np.zeros((M, N))
+            out[lam != 0] = 1.0 / lam[lam != 0]
+            return out
+        monkeypatch.setattr(G, "green_spectrum", bad)
+    elif mutation == "stencil_sign":
+        monkeypatch.setattr(G, "green_spectrum", lambda M, N: -real_green(M, N))
+    elif mutation == "reference_pixel":
+        def bad(gx, gy, M, N, oy, ox):
+            return np.roll(real_div(gx, gy, M, N, oy, ox), 1, axis=-1)
+        monkeypatch.setattr(G, "divergence", bad)
+
+    rng = np.random.default_rng(37)
+    H, W, M, N = 6, 7, 14, 16
+    S, gx, gy = _framed_conservative(rng, H, W)
+    framed_ok = np.max(np.abs(G.solve_fft(gx, gy, M, N) - S)) < 1e-12
+    a = _rand_field(rng, H, W)
+    ls_ok = np.max(np.abs(G.solve_fft(*a, M, N) - G.lstsq_torus(*a, M, N))) < 1e-11
+    assert not (framed_ok and ls_ok), f"mutation {mutation} went unnoticed"
