@@ -1,0 +1,116 @@
+/*
+ * gfc.h - C ABI of the MI355X (gfx950) Green Function Convolution solver.
+ *
+ * The solver turns a gradient field (gx, gy) of an H x W image into the image u whose
+ * gradient is the least-squares fit of (gx, gy) on a zero-padded M x N torus
+ * (Beaini et al., "Fast and Optimal Laplacian Solver for Gradient-Domain Image Editing
+ * using Green Function Convolution", Sec. 2.2-2.3). In the paper's notation:
+ *
+ *   L   = div E, backward differences on the torus                      (eq. (3))
+ *   G^  = F(dirac) / F(laplace) = 1/lambda,                             (eqs. (19)-(22),
+ *         lambda(k,l) = -4 sin^2(pi k/M) - 4 sin^2(pi l/N), G^(0,0) = 0  Algorithm A)
+ *   v   = R(F^-1(F(L) o G^))                                            (eq. (23))
+ *   u   = v[block] - v[0,0]                                             (Algorithm B)
+ *
+ * The H x W block sits at offset (oy, ox) = (floor((M-H)/2), floor((N-W)/2)) of the torus
+ * and the constant is fixed by the grid corner (0,0), which lies in the zero padding.
+ *
+ * Conventions for every entry point below:
+ *  - Pointers named gx, gy, u, du, dgx, dgy are DEVICE pointers to float32 arrays laid out
+ *    [B][H][W], row stride W, image stride H*W, contiguous. The caller owns them.
+ *  - `workspace` is a DEVICE buffer of at least gfc_workspace_size() bytes, 256-byte
+ *    aligned, owned by the caller. Its contents need not be initialised and are undefined
+ *    after a call. Two calls that run concurrently need separate workspaces.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Solve calls only enqueue
+ *    kernels on it: they never allocate, never synchronise and never copy host data.
+ *    Asynchronous kernel errors surface as GFC_E_HIP on a later call.
+ *  - A plan owns its device tables (created by gfc_green_build) and is immutable after
+ *    that call, so it may be used from several streams with separate workspaces.
+ *  - Errors are returned as status codes; nothing is ever thrown across this ABI.
+ */
+#ifndef GFC_H_
+#define GFC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gfc_plan_s* gfc_plan_t;
+typedef struct gfc_ragged_s* gfc_ragged_t;
+
+typedef enum {
+  GFC_OK = 0,
+  GFC_E_ARG = 1,        /* null pointer, non-positive size, B < 0, bad flags           */
+  GFC_E_SIZE = 2,       /* M < H+2 or N < W+2, or N has no supported row-FFT length      */
+  GFC_E_NOT_BUILT = 3,  /* gfc_green_build has not run on this plan                      */
+  GFC_E_WORKSPACE = 4,  /* workspace smaller than gfc_workspace_size()                   */
+  GFC_E_HIP = 5,        /* a HIP runtime call or an earlier asynchronous kernel failed   */
+  GFC_E_OOM = 6         /* device allocation of plan tables failed                       */
+} gfc_status;
+
+/* Plan flags. */
+#define GFC_FLAG_NONE 0u
+
+/*
+ * Create a plan for H x W images solved on an M x N torus (Sec. 2.3.2 zero padding).
+ * M = N = 0 selects the default torus: the smallest even 2/3/5-smooth M >= 2H, N >= 2W.
+ * Requires M >= H + 2, N >= W + 2 and N a supported row-FFT length (even, 2/3/5-smooth,
+ * listed by gfc_supported_length). Host-only: touches no GPU. *out receives the plan.
+ */
+gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned flags);
+
+/*
+ * Build the plan's device tables in float64 on the host and upload them on `stream`:
+ * the row-FFT twiddles and, per column frequency l, the factorisation of the column
+ * Green's function 1/lambda(., l) (eq. (22) restricted to one column of the spectrum).
+ * Idempotent. Synchronises `stream` once (the only synchronising call besides destroy).
+ */
+gfc_status gfc_green_build(gfc_plan_t p, void* stream);
+
+/* Resolved sizes of a plan: any output pointer may be NULL. */
+gfc_status gfc_plan_get(gfc_plan_t p, int* H, int* W, int* M, int* N, int* oy, int* ox);
+
+/* Bytes of workspace needed by gfc_solve_batch and gfc_solve_backward for B images. */
+gfc_status gfc_workspace_size(gfc_plan_t p, int B, size_t* bytes);
+
+/*
+ * Forward solve of B images (eqs. (3), (22), (23) and Algorithm B):
+ *   gx, gy : [B][H][W] float32 gradient fields (forward differences, eq. (1) convention)
+ *   u      : [B][H][W] float32 output potential, u = v[block] - v[0,0]
+ * B = 0 is a no-op. u must not alias gx or gy.
+ */
+gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float* u, int B,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Backward (adjoint) of gfc_solve_batch, for using the solver as a differentiable layer
+ * (Sec. 4): given du = dLoss/du [B][H][W], writes dgx = dLoss/dgx and dgy = dLoss/dgy:
+ *   r = embed(du) - sum(du) * delta_(0,0);  w = g (*) r;
+ *   dgx = -(w[y,x+1] - w[y,x]),  dgy = -(w[y+1,x] - w[y,x])   on the block,
+ * where g is the spatial Green's function (real and even, so its correlation equals its
+ * convolution). Outputs must not alias du.
+ */
+gfc_status gfc_solve_backward(gfc_plan_t p, const float* du, float* dgx, float* dgy, int B,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Tests only: write the plan's Green's spectrum G^ (eq. (22)) as float64 on the HOST,
+ * half spectrum [M][N/2+1] row-major, G^(0,0) = 0. Host-only; needs no build.
+ */
+gfc_status gfc_green_export(gfc_plan_t p, double* half_spectrum_host);
+
+void gfc_plan_destroy(gfc_plan_t p);
+
+/* 1 if N is a supported row-FFT length, else 0. Host-only. */
+int gfc_supported_length(int N);
+
+/* Human-readable status name. */
+const char* gfc_status_str(gfc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFC_H_ */

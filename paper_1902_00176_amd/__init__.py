@@ -1,0 +1,281 @@
+"""MI355X (gfx950) Green Function Convolution solver.
+
+Thin ctypes binding over libgfc.so (the C ABI in include/gfc.h). This module only
+marshals arguments: every step of the solve runs in the library's HIP kernels. PyTorch is
+used for device memory and streams. If the library is missing or no GPU is present, the
+solve calls raise; there is no CPU fallback.
+
+    import paper_1902_00176_amd as gfc
+    u = gfc.solve(gx, gy)                  # gx, gy: float32 CUDA tensors [..., H, W]
+    u = gfc.GFCFunction.apply(gx, gy)      # differentiable (adjoint kernels in backward)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+
+import numpy as np
+
+__all__ = ["GFCError", "Plan", "lib", "lib_path", "solve", "solve_backward", "GFCFunction",
+           "supported_length", "default_grid", "header_functions"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgfc.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "gfc.h")
+_lib = None
+_lock = threading.Lock()
+
+_STATUS = {0: "GFC_OK", 1: "GFC_E_ARG", 2: "GFC_E_SIZE", 3: "GFC_E_NOT_BUILT",
+           4: "GFC_E_WORKSPACE", 5: "GFC_E_HIP", 6: "GFC_E_OOM"}
+
+
+class GFCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where} failed: {_STATUS.get(status, status)}")
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libgfc.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+            L = ctypes.CDLL(_LIB_PATH)
+            vp, i, u, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
+            ip = ctypes.POINTER(ctypes.c_int)
+            L.gfc_plan_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, u]
+            L.gfc_green_build.argtypes = [vp, vp]
+            L.gfc_plan_get.argtypes = [vp, ip, ip, ip, ip, ip, ip]
+            L.gfc_workspace_size.argtypes = [vp, i, ctypes.POINTER(sz)]
+            L.gfc_solve_batch.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_solve_backward.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_green_export.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+            L.gfc_plan_destroy.argtypes = [vp]
+            L.gfc_plan_destroy.restype = None
+            L.gfc_supported_length.argtypes = [i]
+            L.gfc_status_str.argtypes = [i]
+            L.gfc_status_str.restype = ctypes.c_char_p
+            for name in ("gfc_plan_create", "gfc_green_build", "gfc_plan_get",
+                         "gfc_workspace_size", "gfc_solve_batch", "gfc_solve_backward",
+                         "gfc_green_export", "gfc_supported_length"):
+                getattr(L, name).restype = ctypes.c_int
+            _bind_ragged(L)
+            _lib = L
+    return _lib
+
+
+def _bind_ragged(L):
+    if not hasattr(L, "gfc_ragged_create"):
+        return
+    vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.gfc_ragged_create.argtypes = [ctypes.POINTER(vp), i, ip, ip, ctypes.c_uint]
+    L.gfc_ragged_create.restype = ctypes.c_int
+    L.gfc_ragged_build.argtypes = [vp, vp]
+    L.gfc_ragged_build.restype = ctypes.c_int
+    L.gfc_ragged_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    L.gfc_ragged_workspace_size.restype = ctypes.c_int
+    L.gfc_ragged_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    L.gfc_ragged_solve.restype = ctypes.c_int
+    L.gfc_ragged_destroy.argtypes = [vp]
+    L.gfc_ragged_destroy.restype = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/gfc.h declares."""
+    with open(_HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gfc_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise GFCError(st, where)
+
+
+def supported_length(n: int) -> bool:
+    return bool(lib().gfc_supported_length(int(n)))
+
+
+def default_grid(H: int, W: int) -> tuple[int, int]:
+    def sm(n):
+        m = max(2, n)
+        while True:
+            r = m
+            for p in (2, 3, 5):
+                while r % p == 0:
+                    r //= p
+            if r == 1 and m % 2 == 0:
+                return m
+            m += 1
+    return sm(2 * H), sm(2 * W)
+
+
+def _stream_ptr(torch, device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A solver plan for H x W images on an M x N torus (M = N = 0: default torus)."""
+
+    def __init__(self, H: int, W: int, M: int = 0, N: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.gfc_plan_create(ctypes.byref(h), int(H), int(W), int(M), int(N), 0),
+               "gfc_plan_create")
+        self._h = h
+        vals = [ctypes.c_int() for _ in range(6)]
+        _check(L.gfc_plan_get(h, *[ctypes.byref(v) for v in vals]), "gfc_plan_get")
+        self.H, self.W, self.M, self.N, self.oy, self.ox = [v.value for v in vals]
+        self._built_on = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gfc_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, device=None, stream=None):
+        import torch
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self._built_on is None:
+            with torch.cuda.device(dev):
+                _check(lib().gfc_green_build(self._h, _stream_ptr(torch, dev, stream)),
+                       "gfc_green_build")
+            self._built_on = dev
+        elif self._built_on != dev:
+            raise ValueError(f"plan built on {self._built_on}, used on {dev}")
+        return self
+
+    def workspace_size(self, B: int) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().gfc_workspace_size(self._h, int(B), ctypes.byref(n)), "gfc_workspace_size")
+        return n.value
+
+    def green_spectrum(self) -> np.ndarray:
+        out = np.empty((self.M, self.N // 2 + 1), dtype=np.float64)
+        _check(lib().gfc_green_export(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "gfc_green_export")
+        return out
+
+    def _prep(self, *ts):
+        import torch
+        dev = ts[0].device
+        if dev.type != "cuda":
+            raise ValueError("GFC tensors must be on a CUDA (HIP) device")
+        for t in ts:
+            if t.dtype != torch.float32 or t.device != dev:
+                raise TypeError("GFC tensors must be float32 on one device")
+            if t.shape[-2:] != (self.H, self.W):
+                raise ValueError(f"expected [..., {self.H}, {self.W}], got {tuple(t.shape)}")
+        self.build(dev)
+        return torch, dev
+
+    def solve(self, gx, gy, out=None, workspace=None, stream=None):
+        torch, dev = self._prep(gx, gy)
+        if gx.shape != gy.shape:
+            raise ValueError("gx and gy must have the same shape")
+        gx = gx.contiguous()
+        gy = gy.contiguous()
+        B = gx.numel() // (self.H * self.W)
+        u = out if out is not None else torch.empty_like(gx)
+        ws = self._workspace(torch, dev, B, workspace)
+        with torch.cuda.device(dev):
+            _check(lib().gfc_solve_batch(self._h, gx.data_ptr(), gy.data_ptr(), u.data_ptr(), B,
+                                         ws.data_ptr() if ws is not None else None,
+                                         ws.numel() if ws is not None else 0,
+                                         _stream_ptr(torch, dev, stream)), "gfc_solve_batch")
+        return u
+
+    def backward(self, du, workspace=None, stream=None):
+        torch, dev = self._prep(du)
+        du = du.contiguous()
+        B = du.numel() // (self.H * self.W)
+        dgx = torch.empty_like(du)
+        dgy = torch.empty_like(du)
+        ws = self._workspace(torch, dev, B, workspace)
+        with torch.cuda.device(dev):
+            _check(lib().gfc_solve_backward(self._h, du.data_ptr(), dgx.data_ptr(), dgy.data_ptr(), B,
+                                            ws.data_ptr() if ws is not None else None,
+                                            ws.numel() if ws is not None else 0,
+                                            _stream_ptr(torch, dev, stream)), "gfc_solve_backward")
+        return dgx, dgy
+
+    def _workspace(self, torch, dev, B, workspace):
+        if B == 0:
+            return None
+        need = self.workspace_size(B)
+        if workspace is not None:
+            if workspace.numel() * workspace.element_size() < need:
+                raise ValueError(f"workspace too small: need {need} bytes")
+            return workspace
+        return torch.empty(need, dtype=torch.uint8, device=dev)
+
+
+_plans: dict = {}
+
+
+def get_plan(H: int, W: int, M: int = 0, N: int = 0) -> Plan:
+    key = (int(H), int(W), int(M), int(N))
+    with _lock:
+        p = _plans.get(key)
+    if p is None:
+        p = Plan(*key)
+        with _lock:
+            _plans[key] = p
+    return p
+
+
+def solve(gx, gy, M: int = 0, N: int = 0, **kw):
+    """u = GFC(gx, gy) for float32 CUDA tensors of shape [..., H, W]."""
+    return get_plan(gx.shape[-2], gx.shape[-1], M or 0, N or 0).solve(gx, gy, **kw)
+
+
+def solve_backward(du, M: int = 0, N: int = 0, **kw):
+    """(dgx, dgy) = adjoint of the solve applied to du [..., H, W]."""
+    return get_plan(du.shape[-2], du.shape[-1], M or 0, N or 0).backward(du, **kw)
+
+
+def _make_function():
+    import torch
+
+    class GFCFunction(torch.autograd.Function):
+        """u = GFC(gx, gy) as a differentiable layer (the map is linear: nothing is saved)."""
+
+        @staticmethod
+        def forward(ctx, gx, gy, M: int = 0, N: int = 0):
+            ctx.grid = (M, N)
+            return solve(gx, gy, M, N)
+
+        @staticmethod
+        def backward(ctx, du):
+            dgx, dgy = solve_backward(du, *ctx.grid)
+            return dgx, dgy, None, None
+
+    return GFCFunction
+
+
+class _LazyFunction:
+    _f = None
+
+    def __getattr__(self, name):
+        if _LazyFunction._f is None:
+            _LazyFunction._f = _make_function()
+        return getattr(_LazyFunction._f, name)
+
+
+GFCFunction = _LazyFunction()

@@ -1,0 +1,155 @@
+"""Build libgfc.so (HIP, gfx950) in-tree.
+
+The row-pass kernels are templates on the two factors N = N1 * N2 of the row length; one
+translation unit is generated per supported length so they compile in parallel, plus a
+table TU that maps N to its launchers. Output: paper_1902_00176_amd/libgfc.so.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+BUILD = os.path.join(HERE, "_build")
+GEN = os.path.join(BUILD, "gen")
+LIB = os.path.join(HERE, "libgfc.so")
+
+ARCH = "gfx950"
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}"]
+
+
+def smooth235(n: int) -> bool:
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def _pow2ceil(v: int) -> int:
+    return 8 if v <= 8 else 16 if v <= 16 else 32 if v <= 32 else 64
+
+
+def choose_factors(N: int):
+    """(N1, N2) with N1*N2 = N, both 2/3/5-smooth and <= 64: fewest lanes per FFT, then
+    the most balanced split, with N2 (the lane count of the load step) the larger."""
+    best = None
+    for n1 in range(2, 65):
+        if N % n1:
+            continue
+        n2 = N // n1
+        if n2 < 2 or n2 > 64 or not smooth235(n1) or not smooth235(n2) or n2 < n1:
+            continue
+        key = (_pow2ceil(max(n1, n2)), n2 - n1)
+        if best is None or key < best[0]:
+            best = (key, n1, n2)
+    return None if best is None else (best[1], best[2])
+
+
+def default_lengths():
+    """Row lengths compiled into the library: every even 2/3/5-smooth N in [16, 2048] that
+    splits into two factors <= 64, plus 2400 (the 801 x 1200 workload's torus width)."""
+    out = []
+    for n in list(range(16, 2049, 2)) + [2400]:
+        if smooth235(n) and choose_factors(n) is not None:
+            out.append(n)
+    return sorted(set(out))
+
+
+def _lengths_from_env():
+    v = os.environ.get("GFC_ROW_LENGTHS")
+    if not v:
+        return default_lengths()
+    return sorted({int(t) for t in v.replace(",", " ").split()})
+
+
+def generate(lengths):
+    os.makedirs(GEN, exist_ok=True)
+    srcs = []
+    for n in lengths:
+        n1, n2 = choose_factors(n)
+        path = os.path.join(GEN, f"row_{n}.hip")
+        text = (f'#include "gfc_row.h"\n'
+                f"namespace gfc {{\n"
+                f"const RowKernels* gfc_row_entry_{n}() {{\n"
+                f"  static const RowKernels k = GFC_ROW_ENTRY({n1}, {n2});\n"
+                f"  return &k;\n}}\n}}  // namespace gfc\n")
+        _write_if_changed(path, text)
+        srcs.append(path)
+    decl = "".join(f"const RowKernels* gfc_row_entry_{n}();\n" for n in lengths)
+    calls = ",\n      ".join(f"gfc_row_entry_{n}()" for n in lengths)
+    table = (f'#include "gfc_internal.h"\nnamespace gfc {{\n{decl}'
+             f"static const RowKernels* const* table() {{\n"
+             f"  static const RowKernels* const t[] = {{\n      {calls}}};\n  return t;\n}}\n"
+             f"int row_kernel_count() {{ return {len(lengths)}; }}\n"
+             f"const RowKernels* row_kernel_at(int i) {{ return table()[i]; }}\n"
+             f"const RowKernels* find_row_kernels(int N) {{\n"
+             f"  for (int i = 0; i < {len(lengths)}; ++i)\n"
+             f"    if (table()[i]->N == N) return table()[i];\n"
+             f"  return nullptr;\n}}\n}}  // namespace gfc\n")
+    tpath = os.path.join(GEN, "row_table.hip")
+    _write_if_changed(tpath, table)
+    return srcs + [tpath]
+
+
+def _write_if_changed(path, text):
+    if os.path.exists(path):
+        with open(path) as f:
+            if f.read() == text:
+                return
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def _compile(src, obj):
+    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
+    return obj
+
+
+def build(lengths=None, jobs=None, verbose=True, force=False):
+    lengths = lengths or _lengths_from_env()
+    if os.path.isdir(BUILD) and force:
+        shutil.rmtree(BUILD)
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [os.path.join(CSRC, f) for f in ("gfc_api.hip", "gfc_col.hip")] + generate(lengths)
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers.append(os.path.join(INCLUDE, "gfc.h"))
+    newest_hdr = max(os.path.getmtime(h) for h in headers)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    todo = []
+    objs = []
+    for s in srcs:
+        o = os.path.join(BUILD, os.path.basename(s).replace(".hip", ".o"))
+        objs.append(o)
+        if force or not os.path.exists(o) or os.path.getmtime(o) < max(os.path.getmtime(s), newest_hdr):
+            todo.append((s, o))
+    if verbose:
+        print(f"[gfc build] {len(lengths)} row lengths, compiling {len(todo)}/{len(srcs)} units "
+              f"with {jobs} jobs", flush=True)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_compile, s, o) for s, o in todo]
+        for f in cf.as_completed(futs):
+            f.result()
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"[gfc build] wrote {LIB}", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(force="--force" in sys.argv)

@@ -1,0 +1,449 @@
+// gfc_api.hip - plan, float64 table construction and the C ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gfc.h"
+#include "gfc_internal.h"
+
+using namespace gfc;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kLowCols = 16;    // forward: columns l <= K use the split (x-spectral) input
+constexpr int kLowColsB = 64;   // backward: columns l <= Kb take -D_y inside the recursion
+constexpr int kRowStrip = 16;   // rows per slot in the strip-ordered row passes
+constexpr int kColC = 16;       // columns per workgroup in the column pass
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool smooth235(long n) {
+  if (n <= 0) return false;
+  for (long p : {2L, 3L, 5L})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+int smooth_at_least(long n) {
+  long m = n < 2 ? 2 : n;
+  while (!(m % 2 == 0 && smooth235(m))) ++m;
+  return int(m);
+}
+
+// (cos, sin) of 2 pi e / n with exact integer reduction of e
+void cs2pi(long e, long n, double& c, double& s) {
+  e %= n;
+  if (e < 0) e += n;
+  const double t = 2.0 * kPi * double(e) / double(n);
+  c = std::cos(t);
+  s = std::sin(t);
+}
+
+struct ColGeom {
+  int C, nseg, Lseg, Llast;
+};
+
+ColGeom col_geometry(int R) {
+  ColGeom g;
+  int nseg = (R + kColLmax - 1) / kColLmax;
+  g.Lseg = (R + nseg - 1) / nseg;
+  g.nseg = (R + g.Lseg - 1) / g.Lseg;
+  g.Llast = R - (g.nseg - 1) * g.Lseg;
+  int C = kColC;
+  while (C > 1 && C * g.nseg > 1024) C /= 2;
+  g.C = C;
+  return g;
+}
+
+}  // namespace
+
+struct gfc_plan_s {
+  int H = 0, W = 0, M = 0, N = 0, NH = 0, oy = 0, ox = 0, r0 = 0, c0 = 0, K = 0, Kb = 0;
+  unsigned flags = 0;
+  const RowKernels* rk = nullptr;
+  ColGeom gf{}, gb{};
+  int nstrips_f = 0, nstrips_b = 0, npairs = 0;
+  int ntiles_f = 0, ntiles_b = 0, nsums = 0;
+  bool built = false;
+  int device = -1;
+  void* dmem = nullptr;
+  f2 *twA = nullptr, *twB = nullptr, *sx = nullptr, *sxm = nullptr, *dshift = nullptr;
+  ColConst *ccf = nullptr, *ccb = nullptr;
+};
+
+namespace {
+
+void fill_colconst(const gfc_plan_s& p, int R, const ColGeom& g, bool forward,
+                   std::vector<ColConst>& out) {
+  out.assign(p.NH, ColConst{});
+  const double M = p.M, N = p.N;
+  for (int l = 0; l < p.NH; ++l) {
+    ColConst k{};
+    if (l == 0) {
+      k.rho = 1.0;
+      k.inv_rho = 1.0;
+      k.outs = 1.0 / N;
+      out[l] = k;
+      continue;
+    }
+    const double sn = std::sin(kPi * double(l) / N);
+    const double beta = 4.0 * sn * sn;
+    const double sq = std::sqrt(beta + 0.25 * beta * beta);
+    const double den = 1.0 + 0.5 * beta + sq;
+    const double rho = 1.0 / den;
+    const double lr = -std::log1p(0.5 * beta + sq);  // log(rho)
+    auto pw = [&](double n) { return n <= 0 ? 1.0 : std::exp(n * lr); };
+    auto one_minus_pw = [&](double n) { return n <= 0 ? 0.0 : -std::expm1(n * lr); };
+    k.rho = rho;
+    k.inv_rho = den;
+    k.omr = (0.5 * beta + sq) / den;
+    const double one_m_r2 = k.omr * (1.0 + rho);
+    const double inv1mrM = 1.0 / one_minus_pw(M);
+    k.outs = -rho / N;
+    k.rhoL = pw(g.Lseg);
+    k.rhoLl = pw(g.Llast);
+    k.gL = one_minus_pw(2.0 * g.Lseg) / one_m_r2;
+    k.gLl = one_minus_pw(2.0 * g.Llast) / one_m_r2;
+    k.cg = pw(M - R + 1) * inv1mrM;
+    k.rhoRm1 = pw(R - 1);
+    k.cT = rho * one_minus_pw(2.0 * (M - R)) / one_m_r2 * inv1mrM;
+    k.czR = pw(M - R) * inv1mrM;
+    const double r0 = p.r0;
+    k.ra = pw(r0 - R + 1) * one_minus_pw(2.0 * (M - r0)) / one_m_r2;
+    k.rb = pw(M - r0);
+    k.cgd = pw(M - r0) * inv1mrM;
+    k.cTd = pw(r0 - R) * one_minus_pw(2.0 * (M - r0)) / one_m_r2 * inv1mrM;
+    if (forward) {
+      double c, s;
+      cs2pi(long(l) * p.c0, p.N, c, s);
+      const double wgt = (2 * l == p.N) ? 1.0 : 2.0;
+      k.wre = wgt * k.outs * c;
+      k.wim = wgt * k.outs * s;
+    }
+    out[l] = k;
+  }
+}
+
+gfc_status hip_status(hipError_t e) { return e == hipSuccess ? GFC_OK : GFC_E_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* gfc_status_str(gfc_status s) {
+  switch (s) {
+    case GFC_OK: return "GFC_OK";
+    case GFC_E_ARG: return "GFC_E_ARG";
+    case GFC_E_SIZE: return "GFC_E_SIZE";
+    case GFC_E_NOT_BUILT: return "GFC_E_NOT_BUILT";
+    case GFC_E_WORKSPACE: return "GFC_E_WORKSPACE";
+    case GFC_E_HIP: return "GFC_E_HIP";
+    case GFC_E_OOM: return "GFC_E_OOM";
+  }
+  return "GFC_E_UNKNOWN";
+}
+
+int gfc_supported_length(int N) { return find_row_kernels(N) != nullptr ? 1 : 0; }
+
+gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned flags) {
+  if (!out) return GFC_E_ARG;
+  *out = nullptr;
+  if (H < 1 || W < 1 || M < 0 || N < 0 || flags != GFC_FLAG_NONE) return GFC_E_ARG;
+  if (H > (1 << 15) || W > (1 << 15)) return GFC_E_SIZE;
+  if (M == 0) M = smooth_at_least(2L * H);
+  if (N == 0) N = smooth_at_least(2L * W);
+  if (M < H + 2 || N < W + 2) return GFC_E_SIZE;
+  const RowKernels* rk = find_row_kernels(N);
+  if (!rk) return GFC_E_SIZE;
+  auto* p = new (std::nothrow) gfc_plan_s;
+  if (!p) return GFC_E_OOM;
+  p->H = H;
+  p->W = W;
+  p->M = M;
+  p->N = N;
+  p->NH = N / 2 + 1;
+  p->oy = (M - H) / 2;
+  p->ox = (N - W) / 2;
+  p->r0 = M - p->oy;  // grid corner (0,0) relative to the block at the origin
+  p->c0 = N - p->ox;
+  p->K = std::min(kLowCols, p->NH - 1);
+  p->Kb = std::min(kLowColsB, p->NH - 1);
+  p->flags = flags;
+  p->rk = rk;
+  p->gf = col_geometry(H + 1);
+  p->gb = col_geometry(H);
+  p->nstrips_f = (H + 1 + kRowStrip - 1) / kRowStrip;
+  p->nstrips_b = (H + kRowStrip - 1) / kRowStrip;
+  p->npairs = (H + 1) / 2;
+  p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
+  p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
+  p->nsums = (p->npairs + rk->slots - 1) / rk->slots;
+  *out = p;
+  return GFC_OK;
+}
+
+gfc_status gfc_plan_get(gfc_plan_t p, int* H, int* W, int* M, int* N, int* oy, int* ox) {
+  if (!p) return GFC_E_ARG;
+  if (H) *H = p->H;
+  if (W) *W = p->W;
+  if (M) *M = p->M;
+  if (N) *N = p->N;
+  if (oy) *oy = p->oy;
+  if (ox) *ox = p->ox;
+  return GFC_OK;
+}
+
+gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
+  if (!p) return GFC_E_ARG;
+  if (p->built) return GFC_OK;
+  const int N = p->N, N1 = p->rk->N1, N2 = p->rk->N2, NH = p->NH;
+  std::vector<f2> twA(size_t(N1) * N2), twB(size_t(N1) * N2), sx(NH), sxm(NH), dsh(NH);
+  for (int k1 = 0; k1 < N1; ++k1)
+    for (int j = 0; j < N2; ++j) {
+      double c, s;
+      cs2pi(long(k1) * j, N, c, s);
+      twA[size_t(k1) * N2 + j] = f2{float(c), float(-s)};
+      twB[size_t(j) * N1 + k1] = f2{float(c), float(-s)};
+    }
+  for (int l = 0; l < NH; ++l) {
+    double c, s;
+    cs2pi(l, N, c, s);
+    const double h = std::sin(kPi * double(l) / double(N));
+    const double omc = 2.0 * h * h;  // 1 - cos(2 pi l / N)
+    sx[l] = f2{float(omc), float(s)};    // 1 - e^{-i theta}
+    sxm[l] = f2{float(omc), float(-s)};  // 1 - e^{+i theta}
+    cs2pi(long(l) * p->c0, N, c, s);
+    dsh[l] = f2{float(c), float(-s)};    // e^{-2 pi i l c0 / N}
+  }
+  std::vector<ColConst> ccf, ccb;
+  fill_colconst(*p, p->H + 1, p->gf, true, ccf);
+  fill_colconst(*p, p->H, p->gb, false, ccb);
+
+  size_t off = 0;
+  const size_t o_twA = off; off = align256(off + twA.size() * sizeof(f2));
+  const size_t o_twB = off; off = align256(off + twB.size() * sizeof(f2));
+  const size_t o_sx = off; off = align256(off + sx.size() * sizeof(f2));
+  const size_t o_sxm = off; off = align256(off + sxm.size() * sizeof(f2));
+  const size_t o_dsh = off; off = align256(off + dsh.size() * sizeof(f2));
+  const size_t o_ccf = off; off = align256(off + ccf.size() * sizeof(ColConst));
+  const size_t o_ccb = off; off = align256(off + ccb.size() * sizeof(ColConst));
+  std::vector<unsigned char> host(off, 0);
+  std::memcpy(host.data() + o_twA, twA.data(), twA.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twB, twB.data(), twB.size() * sizeof(f2));
+  std::memcpy(host.data() + o_sx, sx.data(), sx.size() * sizeof(f2));
+  std::memcpy(host.data() + o_sxm, sxm.data(), sxm.size() * sizeof(f2));
+  std::memcpy(host.data() + o_dsh, dsh.data(), dsh.size() * sizeof(f2));
+  std::memcpy(host.data() + o_ccf, ccf.data(), ccf.size() * sizeof(ColConst));
+  std::memcpy(host.data() + o_ccb, ccb.data(), ccb.size() * sizeof(ColConst));
+
+  void* d = nullptr;
+  if (hipMalloc(&d, off) != hipSuccess) return GFC_E_OOM;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(d, host.data(), off, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(d);
+    return GFC_E_HIP;
+  }
+  auto* base = static_cast<unsigned char*>(d);
+  p->dmem = d;
+  p->twA = reinterpret_cast<f2*>(base + o_twA);
+  p->twB = reinterpret_cast<f2*>(base + o_twB);
+  p->sx = reinterpret_cast<f2*>(base + o_sx);
+  p->sxm = reinterpret_cast<f2*>(base + o_sxm);
+  p->dshift = reinterpret_cast<f2*>(base + o_dsh);
+  p->ccf = reinterpret_cast<ColConst*>(base + o_ccf);
+  p->ccb = reinterpret_cast<ColConst*>(base + o_ccb);
+  (void)hipGetDevice(&p->device);
+  p->built = true;
+  return GFC_OK;
+}
+
+namespace {
+struct WsLayout {
+  size_t t, side, red, total;
+};
+WsLayout ws_layout(const gfc_plan_s* p, int B) {
+  WsLayout w{};
+  const size_t Bz = size_t(B);
+  const size_t tbytes = Bz * size_t(p->H + 1) * p->NH * sizeof(f2);
+  const size_t sb = Bz * size_t(p->H) * (p->K + 1) * sizeof(f2);
+  const size_t sd = Bz * size_t(p->H) * (p->Kb + 1) * sizeof(f2);
+  const size_t pf = Bz * size_t(p->ntiles_f) * sizeof(double);
+  const size_t ps = Bz * size_t(p->nsums) * sizeof(double);
+  w.t = 0;
+  w.side = align256(tbytes);
+  w.red = w.side + align256(std::max(sb, sd));
+  w.total = w.red + align256(std::max(pf, ps));
+  return w;
+}
+}  // namespace
+
+gfc_status gfc_workspace_size(gfc_plan_t p, int B, size_t* bytes) {
+  if (!p || !bytes || B < 0) return GFC_E_ARG;
+  *bytes = ws_layout(p, B).total;
+  return GFC_OK;
+}
+
+gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float* u, int B,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!gx || !gy || !u || !workspace) return GFC_E_ARG;
+  const WsLayout w = ws_layout(p, B);
+  if (ws_bytes < w.total) return GFC_E_WORKSPACE;
+  auto* ws = static_cast<unsigned char*>(workspace);
+  f2* T = reinterpret_cast<f2*>(ws + w.t);
+  f2* SB = reinterpret_cast<f2*>(ws + w.side);
+  double* partial = reinterpret_cast<double*>(ws + w.red);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long img_t = (long long)(p->H + 1) * p->NH;
+
+  RowFwdArgs a{};
+  a.gx = gx;
+  a.gy = gy;
+  a.T1 = T;
+  a.SB = SB;
+  a.twA = p->twA;
+  a.sx = p->sx;
+  a.H = p->H;
+  a.W = p->W;
+  a.K = p->K;
+  a.strip = kRowStrip;
+  a.nstrips = p->nstrips_f;
+  a.img_in = (long long)p->H * p->W;
+  a.img_t1 = img_t;
+  a.img_sb = (long long)p->H * (p->K + 1);
+  gfc_status st = hip_status(p->rk->fwd(a, B, s));
+  if (st != GFC_OK) return st;
+
+  ColFwdArgs c{};
+  c.T = T;
+  c.SB = SB;
+  c.cc = p->ccf;
+  c.partial = partial;
+  c.H = p->H;
+  c.M = p->M;
+  c.NH = p->NH;
+  c.K = p->K;
+  c.r0 = p->r0;
+  c.C = p->gf.C;
+  c.nseg = p->gf.nseg;
+  c.Lseg = p->gf.Lseg;
+  c.Llast = p->gf.Llast;
+  c.img_t = img_t;
+  c.img_sb = a.img_sb;
+  st = hip_status(launch_col_fwd(c, B, s));
+  if (st != GFC_OK) return st;
+
+  RowInvArgs v{};
+  v.T2 = T;
+  v.u = u;
+  v.partial = partial;
+  v.nparts = p->ntiles_f;
+  v.twB = p->twB;
+  v.H = p->H;
+  v.W = p->W;
+  v.npairs = (p->H + 1) / 2;
+  v.img_t2 = img_t;
+  v.img_u = (long long)p->H * p->W;
+  return hip_status(p->rk->inv(v, B, s));
+}
+
+gfc_status gfc_solve_backward(gfc_plan_t p, const float* du, float* dgx, float* dgy, int B,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!du || !dgx || !dgy || !workspace) return GFC_E_ARG;
+  const WsLayout w = ws_layout(p, B);
+  if (ws_bytes < w.total) return GFC_E_WORKSPACE;
+  auto* ws = static_cast<unsigned char*>(workspace);
+  f2* T = reinterpret_cast<f2*>(ws + w.t);
+  f2* SD = reinterpret_cast<f2*>(ws + w.side);
+  double* sums = reinterpret_cast<double*>(ws + w.red);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long img_t = (long long)(p->H + 1) * p->NH;
+
+  RowBwdFwdArgs a{};
+  a.du = du;
+  a.U = T;
+  a.sums = sums;
+  a.twA = p->twA;
+  a.H = p->H;
+  a.W = p->W;
+  a.npairs = (p->H + 1) / 2;
+  a.img_in = (long long)p->H * p->W;
+  a.img_u = img_t;
+  gfc_status st = hip_status(p->rk->bfwd(a, B, s));
+  if (st != GFC_OK) return st;
+
+  ColBwdArgs c{};
+  c.T = T;
+  c.SD = SD;
+  c.cc = p->ccb;
+  c.sums = sums;
+  c.dshift = p->dshift;
+  c.nsums = p->nsums;
+  c.H = p->H;
+  c.M = p->M;
+  c.NH = p->NH;
+  c.Kb = p->Kb;
+  c.r0 = p->r0;
+  c.C = p->gb.C;
+  c.nseg = p->gb.nseg;
+  c.Lseg = p->gb.Lseg;
+  c.Llast = p->gb.Llast;
+  c.img_t = img_t;
+  c.img_sd = (long long)p->H * (p->Kb + 1);
+  st = hip_status(launch_col_bwd(c, B, s));
+  if (st != GFC_OK) return st;
+
+  RowBwdInvArgs v{};
+  v.Wv = T;
+  v.SD = SD;
+  v.dgx = dgx;
+  v.dgy = dgy;
+  v.twA = p->twA;
+  v.twB = p->twB;
+  v.sxm = p->sxm;
+  v.H = p->H;
+  v.W = p->W;
+  v.Kb = p->Kb;
+  v.strip = kRowStrip;
+  v.nstrips = p->nstrips_b;
+  v.img_w = img_t;
+  v.img_sd = c.img_sd;
+  v.img_out = (long long)p->H * p->W;
+  return hip_status(p->rk->binv(v, B, s));
+}
+
+gfc_status gfc_green_export(gfc_plan_t p, double* out) {
+  if (!p || !out) return GFC_E_ARG;
+  for (int k = 0; k < p->M; ++k) {
+    const double sk = std::sin(kPi * double(k) / double(p->M));
+    for (int l = 0; l < p->NH; ++l) {
+      const double sl = std::sin(kPi * double(l) / double(p->N));
+      const double lam = -4.0 * sk * sk - 4.0 * sl * sl;
+      out[size_t(k) * p->NH + l] = (k == 0 && l == 0) ? 0.0 : 1.0 / lam;
+    }
+  }
+  return GFC_OK;
+}
+
+void gfc_plan_destroy(gfc_plan_t p) {
+  if (!p) return;
+  if (p->dmem) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (p->device >= 0 && cur != p->device) (void)hipSetDevice(p->device);
+    (void)hipFree(p->dmem);
+    if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
+  }
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// gfc_internal.h - argument blocks shared by the host plan code and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gfc {
+
+struct f2 {
+  float x, y;
+};
+
+// ---- row passes -----------------------------------------------------------------------
+// Forward row pass: for each row y in [0, H] of the divergence L (block at the torus
+// origin), T1[y, l] = (1 - w_N^l) Ex^[y, l] + Ey^[y, l] - Ey^[y-1, l] for l > K, and the
+// split form T1[y, l] = (1 - w_N^l) Ex^[y, l], SB[y, l] = Ey^[y, l] for l <= K.
+struct RowFwdArgs {
+  const float* gx;
+  const float* gy;
+  f2* T1;             // [B][H+1][NH]
+  f2* SB;             // [B][H][K+1]
+  const f2* twA;      // [N1][N2]: w_N^(k1 j) (forward sign)
+  const f2* sx;       // [NH]: 1 - w_N^l
+  int H, W, K;
+  int strip;          // rows per slot
+  int nstrips;        // ceil((H+1) / strip)
+  long long img_in, img_t1, img_sb;
+};
+
+// Inverse row pass: rows y in [0, H) of T2 (already scaled by 1/N), two rows per complex
+// inverse FFT; u[y, x] = v[y, x] - v_ref for x in [0, W).
+struct RowInvArgs {
+  const f2* T2;       // [B][>=H][NH] with row stride NH
+  float* u;           // [B][H][W]
+  const double* partial;  // [B][nparts]: v_ref = sum of the partials
+  int nparts;
+  const f2* twB;      // [N2][N1]: w_N^(k j2) (forward sign), conjugated in use
+  int H, W;
+  int npairs;         // ceil(H / 2)
+  long long img_t2, img_u;
+};
+
+// Backward row pass 1: R2C of du rows (two rows per complex FFT), U[y, l], l in [0, NH);
+// also per-block partial sums of du for sum(du).
+struct RowBwdFwdArgs {
+  const float* du;
+  f2* U;              // [B][H+1][NH]
+  double* sums;       // [B][gridDim.x]
+  const f2* twA;
+  int H, W;
+  int npairs;
+  long long img_in, img_u;
+};
+
+// Backward row pass 2: per row y in [0, H): Zx = (1 - w_N^-l) Wv[y, l],
+// Zy = SD[y, l] (l <= Kb) or Wv[y, l] - Wv[y+1, l] (l > Kb); one complex inverse FFT of
+// Zx + i Zy gives (dgx, dgy) on row y.
+struct RowBwdInvArgs {
+  const f2* Wv;       // [B][H+1][NH]
+  const f2* SD;       // [B][H][Kb+1]
+  float* dgx;
+  float* dgy;
+  const f2* twA;      // forward-layout twiddles (used conjugated, thread role of step A)
+  const f2* twB;
+  const f2* sxm;      // [NH]: 1 - w_N^-l
+  int H, W, Kb;
+  int strip, nstrips;
+  long long img_w, img_sd, img_out;
+};
+
+// ---- column pass ------------------------------------------------------------------------
+// Per column frequency l the column Green's function 1/lambda(., l) is applied exactly as
+// -rho (1 - rho S^-1)^-1 (1 - rho S)^-1 on Z_M (two first-order recursions, float64), with
+// rho the root < 1 of rho + 1/rho = 2 + 4 sin^2(pi l / N). All constants are float64 from
+// the host.
+struct ColConst {
+  double rho;       // recursion root (column 0: 1, handled separately)
+  double inv_rho;   // 1 / rho
+  double omr;       // 1 - rho (computed without cancellation)
+  double outs;      // output scale: -rho / N  (column 0: 1 / N)
+  double rhoL;      // rho^Lseg
+  double rhoLl;     // rho^Llast
+  double gL;        // (1 - rho^(2 Lseg)) / (1 - rho^2)
+  double gLl;       // (1 - rho^(2 Llast)) / (1 - rho^2)
+  double cg;        // gamma = cg * c[R-1] (+ cgd * dv)
+  double rhoRm1;    // rho^(R-1)
+  double cT;        // z[R] = cT * w[R-1] + czR * Sum_w (+ cTd * dv)
+  double czR;
+  double ra, rb;    // forward: z[r0] = ra * w[R-1] + rb * z[0]
+  double cgd, cTd;  // backward: Dirac at r0 terms
+  double wre, wim;  // forward: reference term = wre * Re(z[r0]) - wim * Im(z[r0])
+};
+
+struct ColFwdArgs {
+  f2* T;              // in: T1 [B][H+1][NH]; out (in place): T2 rows [0, H)
+  const f2* SB;       // [B][H][K+1]
+  const ColConst* cc; // [NH]
+  double* partial;    // [B][ntiles]
+  int H, M, NH, K, r0;
+  int C, nseg, Lseg, Llast;   // R = H + 1 rows of input
+  long long img_t, img_sb;
+};
+
+struct ColBwdArgs {
+  f2* T;              // in: U [B][H][NH] (row stride NH); out: W rows [0, H]
+  f2* SD;             // out: [B][H][Kb+1]
+  const ColConst* cc; // [NH]
+  const double* sums; // [B][nsums]: sum(du) = sum of the partials
+  const f2* dshift;   // [NH]: w_N^(l c0) (forward sign): row DFT of a Dirac at column c0
+  int nsums;
+  int H, M, NH, Kb, r0;
+  int C, nseg, Lseg, Llast;   // R = H rows of input
+  long long img_t, img_sd;
+};
+
+// launchers (defined in the kernel files)
+struct RowKernels {
+  int N, N1, N2, G, slots;
+  hipError_t (*fwd)(const RowFwdArgs&, int B, hipStream_t);
+  hipError_t (*inv)(const RowInvArgs&, int B, hipStream_t);
+  hipError_t (*bfwd)(const RowBwdFwdArgs&, int B, hipStream_t);
+  hipError_t (*binv)(const RowBwdInvArgs&, int B, hipStream_t);
+};
+const RowKernels* find_row_kernels(int N);
+int row_kernel_count();
+const RowKernels* row_kernel_at(int i);
+
+hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s);
+hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
+constexpr int kColLmax = 32;
+
+}  // namespace gfc

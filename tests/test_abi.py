@@ -1,0 +1,86 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the header
+declares, validates arguments on the host and builds the same Green's spectrum (eq. (22))
+as the oracle. No kernel is launched here."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+gfc = pytest.importorskip("paper_1902_00176_amd")
+if not os.path.exists(gfc.lib_path()):
+    pytest.skip("libgfc.so not built", allow_module_level=True)
+
+
+def test_library_exports_every_header_function():
+    L = gfc.lib()
+    names = gfc.header_functions()
+    assert "gfc_solve_batch" in names and "gfc_solve_backward" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    L = gfc.lib()
+    assert L.gfc_status_str(0) == b"GFC_OK"
+    assert L.gfc_status_str(4) == b"GFC_E_WORKSPACE"
+
+
+@pytest.mark.parametrize("H,W,M,N,status", [
+    (0, 5, 0, 0, 1), (5, -1, 0, 0, 1), (10, 10, 11, 24, 2), (10, 10, 24, 11, 2),
+    (10, 10, 24, 22, 2),   # 22 = 2 * 11 is not 2/3/5-smooth: no row FFT
+    (10, 10, 12, 24, 0), (801, 1200, 0, 0, 0), (64, 64, 128, 128, 0),
+])
+def test_plan_create_validation(H, W, M, N, status):
+    L = gfc.lib()
+    h = ctypes.c_void_p()
+    st = L.gfc_plan_create(ctypes.byref(h), H, W, M, N, 0)
+    assert st == status
+    if st == 0:
+        L.gfc_plan_destroy(h)
+    L.gfc_plan_destroy(None)  # destroying NULL is a no-op
+
+
+def test_default_grid_and_offsets():
+    p = gfc.Plan(801, 1200)
+    assert (p.M, p.N) == (1620, 2400)
+    assert (p.oy, p.ox) == O.block_offset(801, 1200, 1620, 2400)
+    p = gfc.Plan(512, 512)
+    assert (p.M, p.N) == (1024, 1024)
+    p = gfc.Plan(256, 256)
+    assert (p.M, p.N) == (512, 512)
+
+
+def test_solve_without_build_is_an_error_code():
+    L = gfc.lib()
+    p = gfc.Plan(16, 16, 40, 40)
+    st = L.gfc_solve_batch(p.handle, None, None, None, 1, None, 0, None)
+    assert st == 3  # GFC_E_NOT_BUILT: no device touched
+    n = ctypes.c_size_t()
+    assert L.gfc_workspace_size(p.handle, -1, ctypes.byref(n)) == 1
+
+
+def test_workspace_grows_linearly_with_batch():
+    p = gfc.Plan(801, 1200)
+    w1, w2, w100 = p.workspace_size(1), p.workspace_size(2), p.workspace_size(100)
+    assert p.workspace_size(0) == 0
+    assert w2 > w1 and w100 >= 50 * w2 * 0.99
+    # the big term is one [H+1][N/2+1] complex64 array per image
+    assert w100 >= 100 * 802 * 1201 * 8
+
+
+@pytest.mark.parametrize("H,W,M,N", [(5, 6, 12, 16), (64, 64, 128, 128), (100, 37, 210, 80)])
+def test_exported_green_spectrum_matches_oracle(H, W, M, N):
+    p = gfc.Plan(H, W, M, N)
+    G = p.green_spectrum()
+    ref = O.green_spectrum(M, N)[:, : N // 2 + 1]
+    assert G.shape == ref.shape
+    assert np.max(np.abs(G - ref)) <= 1e-15 * np.max(np.abs(ref))
+
+
+def test_supported_lengths_cover_the_workloads():
+    for n in (64, 128, 512, 1024, 2048, 2400, 1620, 1200):
+        assert gfc.supported_length(n), n
+    assert not gfc.supported_length(22)
