@@ -1,0 +1,250 @@
+"""Benchmark of the GFC batched solve on one MI355X.
+
+A step is one forward solve of the 100-image 801x1200 batch on its 1620x2400 torus
+(row pass, column pass, inverse row pass), inputs already resident in HBM. Prints one JSON
+line: solves/s, per-kernel times from HIP events recorded between the passes on the launch
+stream, the roofline of the dominant kernel, forward+backward pairs/s, and the float64 CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-bwd]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+FP32_VALU_PEAK = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, packed FP32 off
+METRIC = "solves/s at 801x1200 B=100 FP32; fwd+bwd & ragged vs plain; % peak HBM BW"
+KERNEL_SOURCES = ["paper_1902_00176_amd/csrc/gfc_row.h", "paper_1902_00176_amd/csrc/gfc_col.hip",
+                  "paper_1902_00176_amd/csrc/gfc_dft.h", "paper_1902_00176_amd/csrc/gfc_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stage_model(H, W, N, K, Kb, kind):
+    """Algorithmic HBM bytes and nominal FLOPs (5 n log2 n per complex FFT) per image."""
+    import math
+    NH = N // 2 + 1
+    fft = 5.0 * N * math.log2(N)
+    if kind == "fwd":
+        return {
+            "k_row_fwd": (8.0 * H * W + 8.0 * (H + 1) * NH + 8.0 * H * (K + 1), (H + 1) * fft),
+            "k_col_fwd": (8.0 * (H + 1) * NH + 8.0 * H * (K + 1) + 8.0 * H * NH, 0.0),
+            "k_row_inv": (8.0 * H * NH + 4.0 * H * W, math.ceil(H / 2) * fft),
+        }
+    return {
+        "k_row_bfwd": (4.0 * H * W + 8.0 * H * NH, math.ceil(H / 2) * fft),
+        "k_col_bwd": (8.0 * H * NH + 8.0 * (H + 1) * NH + 8.0 * H * (Kb + 1), 0.0),
+        "k_row_binv": (8.0 * (H + 1) * NH + 8.0 * H * (Kb + 1) + 8.0 * H * W, H * fft),
+    }
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 PMC runs (profiles/traffic.json), or None
+    when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("fetch_bytes", 0) + k.get("write_bytes", 0)
+
+
+def cpu_baseline(w, budget_s=12.0, max_images=30):
+    import oracle as O
+    n = 0
+    t0 = time.perf_counter()
+    while n < max_images and (n < 2 or time.perf_counter() - t0 < budget_s):
+        O.solve_fft(w.gx[n], w.gy[n], w.M, w.N)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "solves/s", "cores": O.cpu_workers(), "kind": "oracle",
+            "sample": f"{n} images of the 801x1200 batch on the 1620x2400 torus, float64 "
+                      f"scipy.fft oracle, one image at a time ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--batch", type=int, default=100)
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="for rocprofv3 counter runs: one 256 MiB device copy (the scale "
+                         "reference for byte counters), one forward and one backward step")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the solve on a single MI355X "
+              "(the batch shards by image across GPUs with no exchange; see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gfc_synth as synth
+    import paper_1902_00176_amd as gfc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.make_workload("batch801x1200", B=args.batch)
+    B, H, W_ = w.B, w.H, w.W
+    plan = gfc.Plan(H, W_, w.M, w.N).build(dev)
+    gx = torch.from_numpy(w.gx).to(dev)
+    gy = torch.from_numpy(w.gy).to(dev)
+    u = torch.empty_like(gx)
+    ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device=dev)
+    L = gfc.lib()
+    stream = torch.cuda.current_stream(dev)
+    sp = __import__("ctypes").c_void_p(stream.cuda_stream)
+    hp = plan.handle
+
+    def stage_fwd(k):
+        st = L.gfc_solve_batch_stage(hp, k, gx.data_ptr(), gy.data_ptr(), u.data_ptr(), B,
+                                     ws.data_ptr(), ws.numel(), sp)
+        if st != 0:
+            raise gfc.GFCError(st, f"gfc_solve_batch_stage({k})")
+
+    if args.pmc_pass:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        for k in (1, 2, 3):
+            stage_fwd(k)
+        du = torch.randn_like(gx) * 0.1
+        dgx = torch.empty_like(gx)
+        dgy = torch.empty_like(gx)
+        for k in (1, 2, 3):
+            st = L.gfc_solve_backward_stage(hp, k, du.data_ptr(), dgx.data_ptr(), dgy.data_ptr(),
+                                            B, ws.data_ptr(), ws.numel(), sp)
+            if st != 0:
+                raise gfc.GFCError(st, f"gfc_solve_backward_stage({k})")
+        torch.cuda.synchronize()
+        print("pmc pass done", flush=True)
+        return
+
+    for _ in range(args.warmup):
+        for k in (1, 2, 3):
+            stage_fwd(k)
+    torch.cuda.synchronize()
+
+    names = ["k_row_fwd", "k_col_fwd", "k_row_inv"]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        for k in (1, 2, 3):
+            stage_fwd(k)
+            ev[i][k].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    stage_ms = {n: sum(ev[i][k].elapsed_time(ev[i][k + 1]) for i in range(args.steps)) / args.steps
+                for k, n in enumerate(names)}
+
+    model = stage_model(H, W_, w.N, min(16, w.N // 2), min(64, w.N // 2), "fwd")
+    dom = max(stage_ms, key=stage_ms.get)
+    bytes_dom = model[dom][0] * B
+    flops_dom = model[dom][1] * B
+    t_dom = stage_ms[dom] / 1e3
+    hbm_ach = bytes_dom / t_dom
+    alu_ach = flops_dom / t_dom
+    if flops_dom > 0 and alu_ach / FP32_VALU_PEAK > hbm_ach / HBM_PEAK:
+        roof = {"bound": "alu", "achieved": alu_ach / 1e12, "peak": FP32_VALU_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": alu_ach / FP32_VALU_PEAK}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm_ach / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": hbm_ach / HBM_PEAK}
+    traffic = load_traffic(dom)
+    roof["traffic"] = traffic * B if traffic is not None else None
+    roof["kernel"] = dom
+    roof["hbm_frac"] = hbm_ach / HBM_PEAK
+    roof["alu_frac"] = alu_ach / FP32_VALU_PEAK
+
+    total_bytes = sum(v[0] for v in model.values()) * B
+    result = {
+        "metric": METRIC, "value": B / (ms_step / 1e3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "H": H, "W": W_, "M": w.M, "N": w.N, "batch": B},
+        "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "path_hbm_frac": total_bytes / (ms_step / 1e3) / HBM_PEAK,
+        "roofline": roof,
+    }
+
+    if not args.no_bwd:
+        du = torch.randn_like(gx) * 0.1
+        dgx = torch.empty_like(gx)
+        dgy = torch.empty_like(gx)
+        names_b = ["k_row_bfwd", "k_col_bwd", "k_row_binv"]
+
+        def stage_bwd(k):
+            st = L.gfc_solve_backward_stage(hp, k, du.data_ptr(), dgx.data_ptr(), dgy.data_ptr(),
+                                            B, ws.data_ptr(), ws.numel(), sp)
+            if st != 0:
+                raise gfc.GFCError(st, f"gfc_solve_backward_stage({k})")
+
+        for _ in range(2):
+            for k in (1, 2, 3):
+                stage_fwd(k)
+            for k in (1, 2, 3):
+                stage_bwd(k)
+        torch.cuda.synchronize()
+        nb = max(args.steps // 2, 3)
+        evb = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nb)]
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for i in range(nb):
+            for k in (1, 2, 3):
+                stage_fwd(k)
+            evb[i][0].record(stream)
+            for k in (1, 2, 3):
+                stage_bwd(k)
+                evb[i][k].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_pair = t0.elapsed_time(t1) / nb
+        bms = {n: sum(evb[i][k].elapsed_time(evb[i][k + 1]) for i in range(nb)) / nb
+               for k, n in enumerate(names_b)}
+        mb = stage_model(H, W_, w.N, 16, min(64, w.N // 2), "bwd")
+        result["fwd_bwd"] = {"pairs_per_s": B / (ms_pair / 1e3), "ms_per_pair_step": ms_pair,
+                             "stages_ms": {k: round(v, 5) for k, v in bms.items()},
+                             "bwd_hbm_frac": sum(v[0] for v in mb.values()) * B /
+                             (sum(bms.values()) / 1e3) / HBM_PEAK}
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

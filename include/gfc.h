@@ -70,6 +70,18 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
  */
 gfc_status gfc_green_build(gfc_plan_t p, void* stream);
 
+/*
+ * Launch geometry of a plan (results do not depend on it; only speed does). Call before
+ * gfc_green_build; GFC_E_ARG for an unknown name, a value out of range, or a built plan.
+ *   "row_strip" 1..256  rows handled by one FFT slot in the strip-ordered row passes
+ *   "row_ppw"   1..64   row pairs handled by one FFT slot in the pair-ordered row passes
+ *   "col_c"     1..64   (power of two) columns per workgroup in the column pass
+ *   "col_rows"  16|32   most rows per thread in the column pass
+ * The project's autotuner chooses these per (H, W, M, N); host-only.
+ */
+gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value);
+gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value);
+
 /* Resolved sizes of a plan: any output pointer may be NULL. */
 gfc_status gfc_plan_get(gfc_plan_t p, int* H, int* W, int* M, int* N, int* oy, int* ox);
 
@@ -95,6 +107,22 @@ gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float
  */
 gfc_status gfc_solve_backward(gfc_plan_t p, const float* du, float* dgx, float* dgy, int B,
                               void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Instrumentation: run one pass of gfc_solve_batch (stage 1 = row pass: divergence and row
+ * transform; 2 = column pass: the Green's spectrum applied column by column; 3 = inverse
+ * row pass with crop and constant; 0 = all three). Calling stages 1, 2, 3 in order on one
+ * stream with one workspace is exactly gfc_solve_batch; it lets a caller time each kernel
+ * with events between the passes. Arguments a stage does not read may be NULL.
+ */
+gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const float* gy,
+                                 float* u, int B, void* workspace, size_t ws_bytes,
+                                 void* stream);
+
+/* Instrumentation: one pass of gfc_solve_backward (stages as for gfc_solve_batch_stage). */
+gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, float* dgx,
+                                    float* dgy, int B, void* workspace, size_t ws_bytes,
+                                    void* stream);
 
 /*
  * Tests only: write the plan's Green's spectrum G^ (eq. (22)) as float64 on the HOST,

@@ -57,6 +57,10 @@ def lib():
             L.gfc_workspace_size.argtypes = [vp, i, ctypes.POINTER(sz)]
             L.gfc_solve_batch.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_solve_batch_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_solve_backward_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_plan_set_param.argtypes = [vp, ctypes.c_char_p, i]
+            L.gfc_plan_get_param.argtypes = [vp, ctypes.c_char_p, ip]
             L.gfc_green_export.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
             L.gfc_plan_destroy.argtypes = [vp]
             L.gfc_plan_destroy.restype = None
@@ -65,6 +69,8 @@ def lib():
             L.gfc_status_str.restype = ctypes.c_char_p
             for name in ("gfc_plan_create", "gfc_green_build", "gfc_plan_get",
                          "gfc_workspace_size", "gfc_solve_batch", "gfc_solve_backward",
+                         "gfc_solve_batch_stage", "gfc_solve_backward_stage",
+                         "gfc_plan_set_param", "gfc_plan_get_param",
                          "gfc_green_export", "gfc_supported_length"):
                 getattr(L, name).restype = ctypes.c_int
             _bind_ragged(L)
@@ -125,10 +131,37 @@ def _stream_ptr(torch, device, stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-class Plan:
-    """A solver plan for H x W images on an M x N torus (M = N = 0: default torus)."""
+PARAMS = ("row_strip", "row_ppw", "col_c", "col_rows")
+_TUNING_PATH = os.path.join(_HERE, "tuning.json")
+_tuning_db = None
 
-    def __init__(self, H: int, W: int, M: int = 0, N: int = 0):
+
+def tuning_db() -> dict:
+    """Launch parameters chosen by the autotuner (autotune.py), keyed "HxW@MxN"."""
+    global _tuning_db
+    if _tuning_db is None:
+        import json
+        path = os.environ.get("GFC_TUNING_DB", _TUNING_PATH)
+        try:
+            with open(path) as f:
+                _tuning_db = json.load(f).get("plans", {})
+        except (OSError, ValueError):
+            _tuning_db = {}
+    return _tuning_db
+
+
+def tuning_key(H, W, M, N) -> str:
+    return f"{H}x{W}@{M}x{N}"
+
+
+class Plan:
+    """A solver plan for H x W images on an M x N torus (M = N = 0: default torus).
+
+    Launch parameters come from the autotuner's database when it holds this size;
+    `params` overrides them (see gfc_plan_set_param); `tuned=False` keeps the defaults."""
+
+    def __init__(self, H: int, W: int, M: int = 0, N: int = 0, params: dict | None = None,
+                 tuned: bool = True):
         L = lib()
         h = ctypes.c_void_p()
         _check(L.gfc_plan_create(ctypes.byref(h), int(H), int(W), int(M), int(N), 0),
@@ -138,6 +171,25 @@ class Plan:
         _check(L.gfc_plan_get(h, *[ctypes.byref(v) for v in vals]), "gfc_plan_get")
         self.H, self.W, self.M, self.N, self.oy, self.ox = [v.value for v in vals]
         self._built_on = None
+        merged = dict(tuning_db().get(tuning_key(self.H, self.W, self.M, self.N), {})) if tuned else {}
+        merged.update(params or {})
+        for k, v in merged.items():
+            if k in PARAMS:
+                self.set_param(k, v)
+
+    def set_param(self, name: str, value: int):
+        _check(lib().gfc_plan_set_param(self._h, name.encode(), int(value)),
+               f"gfc_plan_set_param({name}={value})")
+
+    def get_param(self, name: str) -> int:
+        v = ctypes.c_int()
+        _check(lib().gfc_plan_get_param(self._h, name.encode(), ctypes.byref(v)),
+               f"gfc_plan_get_param({name})")
+        return v.value
+
+    @property
+    def params(self) -> dict:
+        return {k: self.get_param(k) for k in PARAMS}
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -1,0 +1,154 @@
+"""Autotuner for the GFC launch geometry.
+
+For each image size and torus it times every pass of the forward and backward solve on
+the GPU (HIP events on the launch stream, median of several repetitions) over a grid of
+launch parameters, picks the fastest setting per parameter group and records it in
+tuning.json, which Plan() reads. Parameters only change speed, never results:
+
+  row_strip  rows per FFT slot in the strip-ordered row passes  (row forward, row backward-2)
+  row_ppw    row pairs per FFT slot in the pair-ordered passes  (row inverse, row backward-1)
+  col_c      columns per workgroup in the column pass
+  col_rows   most rows per thread in the column pass (16 | 32)
+
+    python -m paper_1902_00176_amd.autotune --size 801 1200 1620 2400 100 [--write]
+    python -m paper_1902_00176_amd.autotune --workloads [--write]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import itertools
+import json
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import paper_1902_00176_amd as gfc  # noqa: E402
+
+DEFAULT = {"row_strip": 16, "row_ppw": 1, "col_c": 16, "col_rows": 32}
+GRID = {
+    "row_strip": [4, 8, 16, 32],
+    "row_ppw": [1, 2, 4],
+    "col": [(c, r) for c in (4, 8, 16, 32) for r in (16, 32)],
+}
+# the standard workloads: (H, W, M, N, B)
+WORKLOADS = [(801, 1200, 1620, 2400, 100), (512, 512, 1024, 1024, 96),
+             (256, 256, 512, 512, 48), (64, 64, 128, 128, 1)]
+
+
+def time_stages(plan, B, reps=7, torch=None):
+    """Median ms of each forward and backward stage for a batch of B images."""
+    dev = torch.device("cuda:0")
+    H, W = plan.H, plan.W
+    g = torch.randn((B, H, W), device=dev) * 0.1
+    u = torch.empty_like(g)
+    d2 = torch.empty_like(g)
+    ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device=dev)
+    L = gfc.lib()
+    st = torch.cuda.current_stream(dev)
+    sp = ctypes.c_void_p(st.cuda_stream)
+    h = plan.handle
+
+    def f(k):
+        r = L.gfc_solve_batch_stage(h, k, g.data_ptr(), g.data_ptr(), u.data_ptr(), B,
+                                    ws.data_ptr(), ws.numel(), sp)
+        if r:
+            raise gfc.GFCError(r, "gfc_solve_batch_stage")
+
+    def bw(k):
+        r = L.gfc_solve_backward_stage(h, k, g.data_ptr(), u.data_ptr(), d2.data_ptr(), B,
+                                       ws.data_ptr(), ws.numel(), sp)
+        if r:
+            raise gfc.GFCError(r, "gfc_solve_backward_stage")
+
+    times = {n: [] for n in ("fwd1", "fwd2", "fwd3", "bwd1", "bwd2", "bwd3")}
+    for rep in range(reps + 2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        ev[0].record(st)
+        for k in (1, 2, 3):
+            f(k)
+            ev[k].record(st)
+        for k in (1, 2, 3):
+            bw(k)
+            ev[3 + k].record(st)
+        torch.cuda.synchronize()
+        if rep >= 2:
+            names = list(times)
+            for i, n in enumerate(names):
+                times[n].append(ev[i].elapsed_time(ev[i + 1]))
+    return {n: statistics.median(v) for n, v in times.items()}
+
+
+def tune_size(H, W, M, N, B, torch, verbose=True):
+    def run(params):
+        p = gfc.Plan(H, W, M, N, params=params, tuned=False).build()
+        t = time_stages(p, B, torch=torch)
+        del p
+        return t
+
+    best = dict(DEFAULT)
+    log = []
+    # row strip: row forward + row backward-2
+    res = []
+    for v in GRID["row_strip"]:
+        t = run({**DEFAULT, "row_strip": v})
+        res.append((t["fwd1"] + t["bwd3"], v, t))
+        log.append({"row_strip": v, **t})
+    best["row_strip"] = min(res)[1]
+    # row pairs per slot: row inverse + row backward-1
+    res = []
+    for v in GRID["row_ppw"]:
+        t = run({**DEFAULT, "row_ppw": v})
+        res.append((t["fwd3"] + t["bwd1"], v, t))
+        log.append({"row_ppw": v, **t})
+    best["row_ppw"] = min(res)[1]
+    # column pass
+    res = []
+    for c, r in GRID["col"]:
+        t = run({**DEFAULT, "col_c": c, "col_rows": r})
+        res.append((t["fwd2"] + t["bwd2"], (c, r), t))
+        log.append({"col_c": c, "col_rows": r, **t})
+    c, r = min(res)[1]
+    best["col_c"], best["col_rows"] = c, r
+    final = run(best)
+    if verbose:
+        for e in log:
+            print(json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}),
+                  flush=True)
+        print(json.dumps({"size": [H, W, M, N, B], "best": best,
+                          "ms": {k: round(v, 4) for k, v in final.items()}}), flush=True)
+    return best, final
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--size", type=int, nargs=5, action="append", metavar=("H", "W", "M", "N", "B"))
+    ap.add_argument("--workloads", action="store_true")
+    ap.add_argument("--write", action="store_true", help="update tuning.json beside this file")
+    ap.add_argument("--out", help="also write the resulting database to this path")
+    args = ap.parse_args()
+    import torch
+    sizes = [tuple(s) for s in (args.size or [])]
+    if args.workloads:
+        sizes += WORKLOADS
+    db_path = os.path.join(HERE, "tuning.json")
+    try:
+        with open(db_path) as f:
+            db = json.load(f)
+    except (OSError, ValueError):
+        db = {"plans": {}}
+    for H, W, M, N, B in sizes:
+        best, final = tune_size(H, W, M, N, B, torch)
+        db["plans"][gfc.tuning_key(H, W, M, N)] = {**best, "tuned_batch": B,
+                                                   "ms": {k: round(v, 4) for k, v in final.items()}}
+    for path in ([db_path] if args.write else []) + ([args.out] if args.out else []):
+        with open(path, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        print(f"wrote {path}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -16,8 +16,11 @@ namespace {
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kLowCols = 16;    // forward: columns l <= K use the split (x-spectral) input
 constexpr int kLowColsB = 64;   // backward: columns l <= Kb take -D_y inside the recursion
-constexpr int kRowStrip = 16;   // rows per slot in the strip-ordered row passes
-constexpr int kColC = 16;       // columns per workgroup in the column pass
+// Launch geometry defaults; each can be changed per plan with gfc_plan_set_param.
+constexpr int kRowStrip = 16;     // "row_strip": rows per slot in the strip-ordered row passes
+constexpr int kColC = 16;         // "col_c": columns per workgroup in the column pass
+constexpr int kColRows = 32;      // "col_rows": most rows per thread in the column pass (16|32)
+constexpr int kPairsPerSlot = 1;  // "row_ppw": row pairs per slot in the pair-ordered passes
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -46,14 +49,14 @@ struct ColGeom {
   int C, nseg, Lseg, Llast;
 };
 
-ColGeom col_geometry(int R) {
+ColGeom col_geometry(int R, int rows_max, int C_req) {
   ColGeom g;
-  int nseg = (R + kColLmax - 1) / kColLmax;
+  int nseg = (R + rows_max - 1) / rows_max;
   g.Lseg = (R + nseg - 1) / nseg;
   g.nseg = (R + g.Lseg - 1) / g.Lseg;
   g.Llast = R - (g.nseg - 1) * g.Lseg;
-  int C = kColC;
-  while (C > 1 && C * g.nseg > 1024) C /= 2;
+  int C = C_req;
+  while (C > 1 && C * g.nseg > kColMaxThreads) C /= 2;
   g.C = C;
   return g;
 }
@@ -61,10 +64,11 @@ ColGeom col_geometry(int R) {
 }  // namespace
 
 struct gfc_plan_s {
-  int H = 0, W = 0, M = 0, N = 0, NH = 0, oy = 0, ox = 0, r0 = 0, c0 = 0, K = 0, Kb = 0;
+  int H = 0, W = 0, M = 0, N = 0, NH = 0, NHP = 0, KP = 0, KbP = 0, oy = 0, ox = 0, r0 = 0, c0 = 0, K = 0, Kb = 0;
   unsigned flags = 0;
   const RowKernels* rk = nullptr;
   ColGeom gf{}, gb{};
+  int row_strip = kRowStrip, row_ppw = kPairsPerSlot, col_c = kColC, col_rows = kColRows;
   int nstrips_f = 0, nstrips_b = 0, npairs = 0;
   int ntiles_f = 0, ntiles_b = 0, nsums = 0;
   bool built = false;
@@ -129,6 +133,19 @@ void fill_colconst(const gfc_plan_s& p, int R, const ColGeom& g, bool forward,
 
 gfc_status hip_status(hipError_t e) { return e == hipSuccess ? GFC_OK : GFC_E_HIP; }
 
+// launch geometry that follows from the sizes and the tunable parameters
+void derive_geometry(gfc_plan_s* p) {
+  p->gf = col_geometry(p->H + 1, p->col_rows, p->col_c);
+  p->gb = col_geometry(p->H, p->col_rows, p->col_c);
+  p->nstrips_f = (p->H + 1 + p->row_strip - 1) / p->row_strip;
+  p->nstrips_b = (p->H + p->row_strip - 1) / p->row_strip;
+  p->npairs = (p->H + 1) / 2;
+  p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
+  p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
+  const int slots_needed = (p->npairs + p->row_ppw - 1) / p->row_ppw;
+  p->nsums = (slots_needed + p->rk->slots - 1) / p->rk->slots;
+}
+
 }  // namespace
 
 extern "C" {
@@ -171,16 +188,13 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
   p->c0 = N - p->ox;
   p->K = std::min(kLowCols, p->NH - 1);
   p->Kb = std::min(kLowColsB, p->NH - 1);
+  // row strides padded to whole 256-byte lines so column tiles never straddle cache lines
+  p->NHP = (p->NH + 31) / 32 * 32;
+  p->KP = (p->K + 1 + 31) / 32 * 32;
+  p->KbP = (p->Kb + 1 + 31) / 32 * 32;
   p->flags = flags;
   p->rk = rk;
-  p->gf = col_geometry(H + 1);
-  p->gb = col_geometry(H);
-  p->nstrips_f = (H + 1 + kRowStrip - 1) / kRowStrip;
-  p->nstrips_b = (H + kRowStrip - 1) / kRowStrip;
-  p->npairs = (H + 1) / 2;
-  p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
-  p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
-  p->nsums = (p->npairs + rk->slots - 1) / rk->slots;
+  derive_geometry(p);
   *out = p;
   return GFC_OK;
 }
@@ -196,10 +210,43 @@ gfc_status gfc_plan_get(gfc_plan_t p, int* H, int* W, int* M, int* N, int* oy, i
   return GFC_OK;
 }
 
+gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
+  if (!p || !name) return GFC_E_ARG;
+  if (p->built) return GFC_E_ARG;  // the float64 tables depend on the geometry
+  if (!std::strcmp(name, "row_strip")) {
+    if (value < 1 || value > 256) return GFC_E_ARG;
+    p->row_strip = value;
+  } else if (!std::strcmp(name, "row_ppw")) {
+    if (value < 1 || value > 64) return GFC_E_ARG;
+    p->row_ppw = value;
+  } else if (!std::strcmp(name, "col_c")) {
+    if (value < 1 || value > 64 || (value & (value - 1))) return GFC_E_ARG;
+    p->col_c = value;
+  } else if (!std::strcmp(name, "col_rows")) {
+    if (value != 16 && value != 32) return GFC_E_ARG;
+    p->col_rows = value;
+  } else {
+    return GFC_E_ARG;
+  }
+  derive_geometry(p);
+  return GFC_OK;
+}
+
+gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
+  if (!p || !name || !value) return GFC_E_ARG;
+  if (!std::strcmp(name, "row_strip")) *value = p->row_strip;
+  else if (!std::strcmp(name, "row_ppw")) *value = p->row_ppw;
+  else if (!std::strcmp(name, "col_c")) *value = p->gf.C;
+  else if (!std::strcmp(name, "col_rows")) *value = p->col_rows;
+  else return GFC_E_ARG;
+  return GFC_OK;
+}
+
 gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   if (!p) return GFC_E_ARG;
   if (p->built) return GFC_OK;
   const int N = p->N, N1 = p->rk->N1, N2 = p->rk->N2, NH = p->NH;
+  // four-step twiddles w_N^(k1 j): [N1][N2] for the forward step, [N2][N1] for the inverse
   std::vector<f2> twA(size_t(N1) * N2), twB(size_t(N1) * N2), sx(NH), sxm(NH), dsh(NH);
   for (int k1 = 0; k1 < N1; ++k1)
     for (int j = 0; j < N2; ++j) {
@@ -268,9 +315,9 @@ struct WsLayout {
 WsLayout ws_layout(const gfc_plan_s* p, int B) {
   WsLayout w{};
   const size_t Bz = size_t(B);
-  const size_t tbytes = Bz * size_t(p->H + 1) * p->NH * sizeof(f2);
-  const size_t sb = Bz * size_t(p->H) * (p->K + 1) * sizeof(f2);
-  const size_t sd = Bz * size_t(p->H) * (p->Kb + 1) * sizeof(f2);
+  const size_t tbytes = Bz * size_t(p->H + 1) * p->NHP * sizeof(f2);
+  const size_t sb = Bz * size_t(p->H) * p->KP * sizeof(f2);
+  const size_t sd = Bz * size_t(p->H) * p->KbP * sizeof(f2);
   const size_t pf = Bz * size_t(p->ntiles_f) * sizeof(double);
   const size_t ps = Bz * size_t(p->nsums) * sizeof(double);
   w.t = 0;
@@ -287,12 +334,15 @@ gfc_status gfc_workspace_size(gfc_plan_t p, int B, size_t* bytes) {
   return GFC_OK;
 }
 
-gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float* u, int B,
-                           void* workspace, size_t ws_bytes, void* stream) {
-  if (!p || B < 0) return GFC_E_ARG;
+gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const float* gy,
+                                 float* u, int B, void* workspace, size_t ws_bytes,
+                                 void* stream) {
+  if (!p || B < 0 || stage < 0 || stage > 3) return GFC_E_ARG;
   if (!p->built) return GFC_E_NOT_BUILT;
   if (B == 0) return GFC_OK;
-  if (!gx || !gy || !u || !workspace) return GFC_E_ARG;
+  if (!workspace) return GFC_E_ARG;
+  if ((stage == 0 || stage == 1) && (!gx || !gy)) return GFC_E_ARG;
+  if ((stage == 0 || stage == 3) && !u) return GFC_E_ARG;
   const WsLayout w = ws_layout(p, B);
   if (ws_bytes < w.total) return GFC_E_WORKSPACE;
   auto* ws = static_cast<unsigned char*>(workspace);
@@ -300,65 +350,87 @@ gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float
   f2* SB = reinterpret_cast<f2*>(ws + w.side);
   double* partial = reinterpret_cast<double*>(ws + w.red);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const long long img_t = (long long)(p->H + 1) * p->NH;
+  const long long img_t = (long long)(p->H + 1) * p->NHP;
+  const long long img_sb = (long long)p->H * p->KP;
 
-  RowFwdArgs a{};
-  a.gx = gx;
-  a.gy = gy;
-  a.T1 = T;
-  a.SB = SB;
-  a.twA = p->twA;
-  a.sx = p->sx;
-  a.H = p->H;
-  a.W = p->W;
-  a.K = p->K;
-  a.strip = kRowStrip;
-  a.nstrips = p->nstrips_f;
-  a.img_in = (long long)p->H * p->W;
-  a.img_t1 = img_t;
-  a.img_sb = (long long)p->H * (p->K + 1);
-  gfc_status st = hip_status(p->rk->fwd(a, B, s));
-  if (st != GFC_OK) return st;
-
-  ColFwdArgs c{};
-  c.T = T;
-  c.SB = SB;
-  c.cc = p->ccf;
-  c.partial = partial;
-  c.H = p->H;
-  c.M = p->M;
-  c.NH = p->NH;
-  c.K = p->K;
-  c.r0 = p->r0;
-  c.C = p->gf.C;
-  c.nseg = p->gf.nseg;
-  c.Lseg = p->gf.Lseg;
-  c.Llast = p->gf.Llast;
-  c.img_t = img_t;
-  c.img_sb = a.img_sb;
-  st = hip_status(launch_col_fwd(c, B, s));
-  if (st != GFC_OK) return st;
-
-  RowInvArgs v{};
-  v.T2 = T;
-  v.u = u;
-  v.partial = partial;
-  v.nparts = p->ntiles_f;
-  v.twB = p->twB;
-  v.H = p->H;
-  v.W = p->W;
-  v.npairs = (p->H + 1) / 2;
-  v.img_t2 = img_t;
-  v.img_u = (long long)p->H * p->W;
-  return hip_status(p->rk->inv(v, B, s));
+  if (stage == 0 || stage == 1) {
+    RowFwdArgs a{};
+    a.gx = gx;
+    a.gy = gy;
+    a.T1 = T;
+    a.SB = SB;
+    a.twA = p->twA;
+    a.sx = p->sx;
+    a.H = p->H;
+    a.W = p->W;
+    a.K = p->K;
+    a.KP = p->KP;
+    a.strip = p->row_strip;
+    a.nstrips = p->nstrips_f;
+    a.img_in = (long long)p->H * p->W;
+    a.img_t1 = img_t;
+    a.img_sb = img_sb;
+    const gfc_status st = hip_status(p->rk->fwd(a, B, s));
+    if (st != GFC_OK) return st;
+  }
+  if (stage == 0 || stage == 2) {
+    ColFwdArgs c{};
+    c.T = T;
+    c.SB = SB;
+    c.cc = p->ccf;
+    c.partial = partial;
+    c.H = p->H;
+    c.M = p->M;
+    c.NH = p->NH;
+    c.NHP = p->NHP;
+    c.K = p->K;
+    c.KP = p->KP;
+    c.r0 = p->r0;
+    c.C = p->gf.C;
+    c.nseg = p->gf.nseg;
+    c.Lseg = p->gf.Lseg;
+    c.Llast = p->gf.Llast;
+    c.img_t = img_t;
+    c.img_sb = img_sb;
+    const gfc_status st = hip_status(launch_col_fwd(c, B, s));
+    if (st != GFC_OK) return st;
+  }
+  if (stage == 0 || stage == 3) {
+    RowInvArgs v{};
+    v.T2 = T;
+    v.u = u;
+    v.partial = partial;
+    v.nparts = p->ntiles_f;
+    v.twB = p->twB;
+    v.H = p->H;
+    v.W = p->W;
+    v.npairs = (p->H + 1) / 2;
+    v.ppw = p->row_ppw;
+    v.img_t2 = img_t;
+    v.img_u = (long long)p->H * p->W;
+    const gfc_status st = hip_status(p->rk->inv(v, B, s));
+    if (st != GFC_OK) return st;
+  }
+  return GFC_OK;
 }
 
-gfc_status gfc_solve_backward(gfc_plan_t p, const float* du, float* dgx, float* dgy, int B,
-                              void* workspace, size_t ws_bytes, void* stream) {
+gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float* u, int B,
+                           void* workspace, size_t ws_bytes, void* stream) {
   if (!p || B < 0) return GFC_E_ARG;
   if (!p->built) return GFC_E_NOT_BUILT;
   if (B == 0) return GFC_OK;
-  if (!du || !dgx || !dgy || !workspace) return GFC_E_ARG;
+  return gfc_solve_batch_stage(p, 0, gx, gy, u, B, workspace, ws_bytes, stream);
+}
+
+gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, float* dgx,
+                                    float* dgy, int B, void* workspace, size_t ws_bytes,
+                                    void* stream) {
+  if (!p || B < 0 || stage < 0 || stage > 3) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!workspace) return GFC_E_ARG;
+  if ((stage == 0 || stage == 1) && !du) return GFC_E_ARG;
+  if ((stage == 0 || stage == 3) && (!dgx || !dgy)) return GFC_E_ARG;
   const WsLayout w = ws_layout(p, B);
   if (ws_bytes < w.total) return GFC_E_WORKSPACE;
   auto* ws = static_cast<unsigned char*>(workspace);
@@ -366,59 +438,77 @@ gfc_status gfc_solve_backward(gfc_plan_t p, const float* du, float* dgx, float* 
   f2* SD = reinterpret_cast<f2*>(ws + w.side);
   double* sums = reinterpret_cast<double*>(ws + w.red);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const long long img_t = (long long)(p->H + 1) * p->NH;
+  const long long img_t = (long long)(p->H + 1) * p->NHP;
+  const long long img_sd = (long long)p->H * p->KbP;
 
-  RowBwdFwdArgs a{};
-  a.du = du;
-  a.U = T;
-  a.sums = sums;
-  a.twA = p->twA;
-  a.H = p->H;
-  a.W = p->W;
-  a.npairs = (p->H + 1) / 2;
-  a.img_in = (long long)p->H * p->W;
-  a.img_u = img_t;
-  gfc_status st = hip_status(p->rk->bfwd(a, B, s));
-  if (st != GFC_OK) return st;
+  if (stage == 0 || stage == 1) {
+    RowBwdFwdArgs a{};
+    a.du = du;
+    a.U = T;
+    a.sums = sums;
+    a.twA = p->twA;
+    a.H = p->H;
+    a.W = p->W;
+    a.npairs = (p->H + 1) / 2;
+    a.ppw = p->row_ppw;
+    a.img_in = (long long)p->H * p->W;
+    a.img_u = img_t;
+    const gfc_status st = hip_status(p->rk->bfwd(a, B, s));
+    if (st != GFC_OK) return st;
+  }
+  if (stage == 0 || stage == 2) {
+    ColBwdArgs c{};
+    c.T = T;
+    c.SD = SD;
+    c.cc = p->ccb;
+    c.sums = sums;
+    c.dshift = p->dshift;
+    c.nsums = p->nsums;
+    c.H = p->H;
+    c.M = p->M;
+    c.NH = p->NH;
+    c.NHP = p->NHP;
+    c.Kb = p->Kb;
+    c.KbP = p->KbP;
+    c.r0 = p->r0;
+    c.C = p->gb.C;
+    c.nseg = p->gb.nseg;
+    c.Lseg = p->gb.Lseg;
+    c.Llast = p->gb.Llast;
+    c.img_t = img_t;
+    c.img_sd = img_sd;
+    const gfc_status st = hip_status(launch_col_bwd(c, B, s));
+    if (st != GFC_OK) return st;
+  }
+  if (stage == 0 || stage == 3) {
+    RowBwdInvArgs v{};
+    v.Wv = T;
+    v.SD = SD;
+    v.dgx = dgx;
+    v.dgy = dgy;
+    v.twB = p->twB;
+    v.sxm = p->sxm;
+    v.H = p->H;
+    v.W = p->W;
+    v.Kb = p->Kb;
+    v.KbP = p->KbP;
+    v.strip = p->row_strip;
+    v.nstrips = p->nstrips_b;
+    v.img_w = img_t;
+    v.img_sd = img_sd;
+    v.img_out = (long long)p->H * p->W;
+    const gfc_status st = hip_status(p->rk->binv(v, B, s));
+    if (st != GFC_OK) return st;
+  }
+  return GFC_OK;
+}
 
-  ColBwdArgs c{};
-  c.T = T;
-  c.SD = SD;
-  c.cc = p->ccb;
-  c.sums = sums;
-  c.dshift = p->dshift;
-  c.nsums = p->nsums;
-  c.H = p->H;
-  c.M = p->M;
-  c.NH = p->NH;
-  c.Kb = p->Kb;
-  c.r0 = p->r0;
-  c.C = p->gb.C;
-  c.nseg = p->gb.nseg;
-  c.Lseg = p->gb.Lseg;
-  c.Llast = p->gb.Llast;
-  c.img_t = img_t;
-  c.img_sd = (long long)p->H * (p->Kb + 1);
-  st = hip_status(launch_col_bwd(c, B, s));
-  if (st != GFC_OK) return st;
-
-  RowBwdInvArgs v{};
-  v.Wv = T;
-  v.SD = SD;
-  v.dgx = dgx;
-  v.dgy = dgy;
-  v.twA = p->twA;
-  v.twB = p->twB;
-  v.sxm = p->sxm;
-  v.H = p->H;
-  v.W = p->W;
-  v.Kb = p->Kb;
-  v.strip = kRowStrip;
-  v.nstrips = p->nstrips_b;
-  v.img_w = img_t;
-  v.img_sd = c.img_sd;
-  v.img_out = (long long)p->H * p->W;
-  return hip_status(p->rk->binv(v, B, s));
+gfc_status gfc_solve_backward(gfc_plan_t p, const float* du, float* dgx, float* dgy, int B,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  return gfc_solve_backward_stage(p, 0, du, dgx, dgy, B, workspace, ws_bytes, stream);
 }
 
 gfc_status gfc_green_export(gfc_plan_t p, double* out) {

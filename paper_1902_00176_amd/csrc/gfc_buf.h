@@ -1,0 +1,40 @@
+// gfc_buf.h - raw buffer loads and stores for gfx950.
+//
+// A buffer descriptor (four SGPRs) holds the base address and the byte range; each access
+// takes a 32-bit per-lane byte offset (VGPR) and a uniform byte offset (SGPR). Rows that are
+// far apart then cost one scalar add instead of a 64-bit address pair per lane, and an
+// access past the range reads 0 / is dropped by the hardware.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gfc {
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// descriptor word 3 for raw (untyped, stride 0) buffers on gfx9-family parts
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_buf(const void* base, long long bytes) {
+  const int n = bytes > 0x7fffffffLL ? 0x7fffffff : int(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, n, kBufWord3);
+}
+
+struct f2b {
+  float x, y;
+};
+
+__device__ __forceinline__ f2b bld2(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(f2b, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float bld1(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bst2(rsrc_t r, float x, float y, int voff, int soff) {
+  using v2u = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, f2b{x, y}), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bst1(rsrc_t r, float x, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+}
+
+}  // namespace gfc

@@ -16,11 +16,11 @@ struct f2 {
 struct RowFwdArgs {
   const float* gx;
   const float* gy;
-  f2* T1;             // [B][H+1][NH]
-  f2* SB;             // [B][H][K+1]
-  const f2* twA;      // [N1][N2]: w_N^(k1 j) (forward sign)
+  f2* T1;             // [B][H+1][NHP]  (NHP = NH rounded up to 32: row stride)
+  f2* SB;             // [B][H][KP]     (KP = side-array row stride >= K + 1)
+  const f2* twA;      // [N1][N2]: w_N^(k1 j), forward sign
   const f2* sx;       // [NH]: 1 - w_N^l
-  int H, W, K;
+  int H, W, K, KP;
   int strip;          // rows per slot
   int nstrips;        // ceil((H+1) / strip)
   long long img_in, img_t1, img_sb;
@@ -33,9 +33,10 @@ struct RowInvArgs {
   float* u;           // [B][H][W]
   const double* partial;  // [B][nparts]: v_ref = sum of the partials
   int nparts;
-  const f2* twB;      // [N2][N1]: w_N^(k j2) (forward sign), conjugated in use
+  const f2* twB;      // [N2][N1]: w_N^(k j2), forward sign, conjugated in use
   int H, W;
   int npairs;         // ceil(H / 2)
+  int ppw;            // row pairs per slot
   long long img_t2, img_u;
 };
 
@@ -48,6 +49,7 @@ struct RowBwdFwdArgs {
   const f2* twA;
   int H, W;
   int npairs;
+  int ppw;
   long long img_in, img_u;
 };
 
@@ -56,13 +58,12 @@ struct RowBwdFwdArgs {
 // Zx + i Zy gives (dgx, dgy) on row y.
 struct RowBwdInvArgs {
   const f2* Wv;       // [B][H+1][NH]
-  const f2* SD;       // [B][H][Kb+1]
+  const f2* SD;       // [B][H][KbP]
   float* dgx;
   float* dgy;
-  const f2* twA;      // forward-layout twiddles (used conjugated, thread role of step A)
   const f2* twB;
   const f2* sxm;      // [NH]: 1 - w_N^-l
-  int H, W, Kb;
+  int H, W, Kb, KbP;
   int strip, nstrips;
   long long img_w, img_sd, img_out;
 };
@@ -95,7 +96,8 @@ struct ColFwdArgs {
   const f2* SB;       // [B][H][K+1]
   const ColConst* cc; // [NH]
   double* partial;    // [B][ntiles]
-  int H, M, NH, K, r0;
+  int ntiles, tile0;  // column tiles in all; first tile of this launch (set by the launcher)
+  int H, M, NH, NHP, K, KP, r0;
   int C, nseg, Lseg, Llast;   // R = H + 1 rows of input
   long long img_t, img_sb;
 };
@@ -107,7 +109,7 @@ struct ColBwdArgs {
   const double* sums; // [B][nsums]: sum(du) = sum of the partials
   const f2* dshift;   // [NH]: w_N^(l c0) (forward sign): row DFT of a Dirac at column c0
   int nsums;
-  int H, M, NH, Kb, r0;
+  int H, M, NH, NHP, Kb, KbP, r0;
   int C, nseg, Lseg, Llast;   // R = H rows of input
   long long img_t, img_sd;
 };
@@ -126,6 +128,6 @@ const RowKernels* row_kernel_at(int i);
 
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s);
 hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
-constexpr int kColLmax = 32;
+constexpr int kColMaxThreads = 512;  // largest column-pass workgroup
 
 }  // namespace gfc

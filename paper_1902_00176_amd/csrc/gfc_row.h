@@ -10,6 +10,7 @@
 // sequences share one complex FFT (packing a + i b), separated by the mirror bins N - l
 // through a second LDS pass in natural order.
 #pragma once
+#include "gfc_buf.h"
 #include "gfc_dft.h"
 #include "gfc_internal.h"
 
@@ -26,6 +27,7 @@ struct RowCfg {
   static constexpr int SB = (N1 % 2 == 0) ? N1 + 1 : N1;  // odd LDS stride, inverse transpose
   static constexpr int LDSC = cmax(cmax(N1 * SA, N2 * SB), N);  // floats per plane per slot
   static constexpr int NH = N / 2 + 1;
+  static constexpr int NHP = ((NH + 31) / 32) * 32;  // row stride of spectra (256-byte rows)
   static constexpr int NI = (NH + G - 1) / G;  // half-spectrum bins owned per lane
   static_assert(N1 <= 64 && N2 <= 64, "row factors must fit one wavefront");
 };
@@ -36,30 +38,50 @@ __device__ __forceinline__ cx ld2(const f2* p) {
 }
 __device__ __forceinline__ void st2(f2* p, cx v) { *p = f2{v.x, v.y}; }
 
+// A slot never spans two wavefronts, so its LDS exchanges only need the wavefront to be in
+// step: release/acquire fences at wavefront scope around a wave barrier.
+__device__ __forceinline__ void slot_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// An integer the optimiser must treat as changed at each loop iteration: added to the uniform
+// offsets of loop-invariant table loads so they are issued where used instead of being
+// hoisted out of the row loop and held live. Empty asm: no instruction is emitted.
+__device__ __forceinline__ int fresh_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
 // Forward four-step body. On entry lane j < N2 holds a[y1] = z[N2*y1 + j]; on exit the
 // spectrum Z is in LDS (re/im planes) in natural order.
 template <int N1, int N2>
 __device__ __forceinline__ void fwd_fft_to_lds(cx (&a)[N1], float* re, float* im, int lane,
-                                               const f2* __restrict__ twA) {
+                                               rsrc_t twA, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N2) {
     Dft<N1, -1>::run(a);
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], ld2(twA + k1 * N2 + lane));
+    for (int k1 = 1; k1 < N1; ++k1) {
+      const f2b w = bld2(twA, lane * 8, tz + k1 * N2 * 8);
+      a[k1] = cmul(a[k1], cx{w.x, w.y});
+    }
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) {
       re[k1 * C::SA + lane] = a[k1].x;
       im[k1 * C::SA + lane] = a[k1].y;
     }
   }
-  __syncthreads();
+  slot_sync();
   cx b[N2];
   if (lane < N1) {
 #pragma unroll
     for (int j = 0; j < N2; ++j) b[j] = {re[lane * C::SA + j], im[lane * C::SA + j]};
     Dft<N2, -1>::run(b);
   }
-  __syncthreads();
+  slot_sync();
   if (lane < N1) {
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
@@ -67,27 +89,29 @@ __device__ __forceinline__ void fwd_fft_to_lds(cx (&a)[N1], float* re, float* im
       im[lane + N1 * k2] = b[k2].y;
     }
   }
-  __syncthreads();
+  slot_sync();
 }
 
 // Inverse four-step body. On entry lane k < N1 holds b[k2] = Z[k + N1*k2]; on exit lane
 // j < N2 holds a[j1] = z[j + N2*j1] (unnormalised inverse DFT).
 template <int N1, int N2>
 __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], float* re,
-                                                  float* im, int lane,
-                                                  const f2* __restrict__ twB) {
+                                                  float* im, int lane, rsrc_t twB, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N1) {
     Dft<N2, +1>::run(b);
 #pragma unroll
-    for (int j2 = 1; j2 < N2; ++j2) b[j2] = cmulconj(b[j2], ld2(twB + j2 * N1 + lane));
+    for (int j2 = 1; j2 < N2; ++j2) {
+      const f2b w = bld2(twB, lane * 8, tz + j2 * N1 * 8);
+      b[j2] = cmulconj(b[j2], cx{w.x, w.y});
+    }
 #pragma unroll
     for (int j2 = 0; j2 < N2; ++j2) {
       re[j2 * C::SB + lane] = b[j2].x;
       im[j2 * C::SB + lane] = b[j2].y;
     }
   }
-  __syncthreads();
+  slot_sync();
   if (lane < N2) {
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) a[k1] = {re[lane * C::SB + k1], im[lane * C::SB + k1]};
@@ -112,32 +136,36 @@ k_row_fwd(RowFwdArgs p) {
   const int strip = blockIdx.x * SLOTS + slot;
   const bool strip_ok = strip < p.nstrips;
   const int y0 = strip * p.strip;
-  const float* __restrict__ gx = p.gx + b * p.img_in;
-  const float* __restrict__ gy = p.gy + b * p.img_in;
-  f2* __restrict__ T1 = p.T1 + b * p.img_t1;
-  f2* __restrict__ SBo = p.SB + b * p.img_sb;
-  const int K1 = p.K + 1;
+  const int K1 = p.KP;
+  const rsrc_t rgx = make_buf(p.gx + b * p.img_in, p.img_in * 4);
+  const rsrc_t rgy = make_buf(p.gy + b * p.img_in, p.img_in * 4);
+  const rsrc_t rT1 = make_buf(p.T1 + b * p.img_t1, p.img_t1 * 8);
+  const rsrc_t rSB = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
+  const rsrc_t rtw = make_buf(p.twA, (long long)C::N * 8);
+  const rsrc_t rsx = make_buf(p.sx, (long long)C::NH * 8);
 
   cx prev[C::NI];
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) prev[i] = {0.f, 0.f};
 
   for (int it = 0; it <= p.strip; ++it) {
+    const int tz = fresh_zero();
     const int y = y0 - 1 + it;
     const bool row_in = strip_ok && y >= 0 && y < p.H;
     cx a[N1];
     if (lane < N2) {
+      const int vo = (y * p.W + lane) * 4;
 #pragma unroll
       for (int y1 = 0; y1 < N1; ++y1) {
         const int x = N2 * y1 + lane;
         if (row_in && x < p.W) {
-          a[y1] = {gx[(long long)y * p.W + x], gy[(long long)y * p.W + x]};
+          a[y1] = {bld1(rgx, vo, N2 * y1 * 4), bld1(rgy, vo, N2 * y1 * 4)};
         } else {
           a[y1] = {0.f, 0.f};
         }
       }
     }
-    fwd_fft_to_lds<N1, N2>(a, re, im, lane, p.twA);
+    fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
     const bool emit = strip_ok && it > 0 && y <= p.H;
 #pragma unroll
     for (int i = 0; i < C::NI; ++i) {
@@ -148,23 +176,25 @@ k_row_fwd(RowFwdArgs p) {
         const cx ex = {0.5f * (ar + br), 0.5f * (ai - bi)};
         const cx ey = {0.5f * (ai + bi), 0.5f * (br - ar)};
         if (emit) {
-          cx t = cmul(ld2(p.sx + l), ex);
+          const f2b sv = bld2(rsx, lane * 8, tz + C::G * i * 8);
+          cx t = cmul(cx{sv.x, sv.y}, ex);
           if (l > p.K) {
             t = cadd(t, csub(ey, prev[i]));
           } else if (y < p.H) {
-            st2(SBo + (long long)y * K1 + l, ey);
+            bst2(rSB, ey.x, ey.y, (y * K1 + lane) * 8, C::G * i * 8);
           }
-          st2(T1 + (long long)y * C::NH + l, t);
+          bst2(rT1, t.x, t.y, (y * C::NHP + lane) * 8, C::G * i * 8);
         }
         prev[i] = ey;
       }
     }
-    __syncthreads();
+    slot_sync();
   }
 }
 
 // ---------------------------------------------------------------------------------------
 // Inverse row pass (row C2R of eq. (23), real part, crop and Algorithm B's constant).
+// Each slot handles p.ppw pairs of rows, two rows per complex inverse FFT.
 template <int N1, int N2, int SLOTS>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_inv(RowInvArgs p) {
@@ -176,41 +206,51 @@ k_row_inv(RowInvArgs p) {
   float* re = s_re[slot];
   float* im = s_im[slot];
   const int b = blockIdx.y;
-  const int q = blockIdx.x * SLOTS + slot;
-  const bool ok = q < p.npairs;
-  const int y1 = 2 * q, y2 = 2 * q + 1;
-  const bool has2 = ok && y2 < p.H;
-  const f2* __restrict__ T2 = p.T2 + b * p.img_t2;
-  float* __restrict__ u = p.u + b * p.img_u;
+  const rsrc_t rT2 = make_buf(p.T2 + b * p.img_t2, p.img_t2 * 8);
+  const rsrc_t ru = make_buf(p.u + b * p.img_u, p.img_u * 4);
+  const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
 
+  // v_ref = sum of the column pass's per-tile partials: lane-strided sums, then a fixed-order
+  // butterfly across the slot (every lane ends with the same, deterministic total)
   double vr = 0.0;
-  for (int j = 0; j < p.nparts; ++j) vr += p.partial[(long long)b * p.nparts + j];
+  for (int j = lane; j < p.nparts; j += C::G) vr += p.partial[(long long)b * p.nparts + j];
+#pragma unroll
+  for (int off = C::G / 2; off > 0; off >>= 1) vr += __shfl_xor(vr, off, C::G);
   const float vref = float(vr);
 
-  cx bz[N2];
-  if (lane < N1) {
+  for (int r = 0; r < p.ppw; ++r) {
+    const int tz = fresh_zero();
+    const int q = (blockIdx.x * SLOTS + slot) * p.ppw + r;
+    const bool ok = q < p.npairs;
+    const int y1 = 2 * q, y2 = 2 * q + 1;
+    const bool has2 = ok && y2 < p.H;
+    cx bz[N2];
+    if (lane < N1) {
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
-      const int kk = lane + N1 * k2;
-      cx X1 = {0.f, 0.f}, X2 = {0.f, 0.f};
-      const int m = kk < C::NH ? kk : C::N - kk;
-      if (ok) X1 = ld2(T2 + (long long)y1 * C::NH + m);
-      if (has2) X2 = ld2(T2 + (long long)y2 * C::NH + m);
-      if (kk < C::NH) bz[k2] = {X1.x - X2.y, X1.y + X2.x};
-      else bz[k2] = {X1.x + X2.y, X2.x - X1.y};
-    }
-  }
-  cx a[N1];
-  inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, p.twB);
-  if (lane < N2 && ok) {
-#pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) {
-      const int x = lane + N2 * j1;
-      if (x < p.W) {
-        u[(long long)y1 * p.W + x] = a[j1].x - vref;
-        if (has2) u[(long long)y2 * p.W + x] = a[j1].y - vref;
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int kk = lane + N1 * k2;
+        const int m = kk < C::NH ? kk : C::N - kk;
+        f2b X1 = {0.f, 0.f}, X2 = {0.f, 0.f};
+        if (ok) X1 = bld2(rT2, (y1 * C::NHP + m) * 8, 0);
+        if (has2) X2 = bld2(rT2, (y2 * C::NHP + m) * 8, 0);
+        if (kk < C::NH) bz[k2] = {X1.x - X2.y, X1.y + X2.x};
+        else bz[k2] = {X1.x + X2.y, X2.x - X1.y};
       }
     }
+    cx a[N1];
+    inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
+    if (lane < N2 && ok) {
+      const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int x = lane + N2 * j1;
+        if (x < p.W) {
+          bst1(ru, a[j1].x - vref, v1, N2 * j1 * 4);
+          if (has2) bst1(ru, a[j1].y - vref, v2, N2 * j1 * 4);
+        }
+      }
+    }
+    slot_sync();
   }
 }
 
@@ -228,40 +268,50 @@ k_row_bfwd(RowBwdFwdArgs p) {
   float* re = s_re[slot];
   float* im = s_im[slot];
   const int b = blockIdx.y;
-  const int q = blockIdx.x * SLOTS + slot;
-  const bool ok = q < p.npairs;
-  const int y1 = 2 * q, y2 = 2 * q + 1;
-  const bool has2 = ok && y2 < p.H;
-  const float* __restrict__ du = p.du + b * p.img_in;
-  f2* __restrict__ U = p.U + b * p.img_u;
+  const rsrc_t rdu = make_buf(p.du + b * p.img_in, p.img_in * 4);
+  const rsrc_t rU = make_buf(p.U + b * p.img_u, p.img_u * 8);
+  const rsrc_t rtw = make_buf(p.twA, (long long)C::N * 8);
 
-  cx a[N1];
-  float lsum = 0.f;
-  if (lane < N2) {
+  double lsum = 0.0;
+  for (int r = 0; r < p.ppw; ++r) {
+    const int tz = fresh_zero();
+    const int q = (blockIdx.x * SLOTS + slot) * p.ppw + r;
+    const bool ok = q < p.npairs;
+    const int y1 = 2 * q, y2 = 2 * q + 1;
+    const bool has2 = ok && y2 < p.H;
+    cx a[N1];
+    float rs = 0.f;
+    if (lane < N2) {
+      const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) {
-      const int x = N2 * j1 + lane;
-      float r = 0.f, s = 0.f;
-      if (ok && x < p.W) r = du[(long long)y1 * p.W + x];
-      if (has2 && x < p.W) s = du[(long long)y2 * p.W + x];
-      a[j1] = {r, s};
-      lsum += r + s;
-    }
-  }
-  s_sum[threadIdx.x] = double(lsum);
-  fwd_fft_to_lds<N1, N2>(a, re, im, lane, p.twA);
-  if (ok) {
-#pragma unroll
-    for (int i = 0; i < C::NI; ++i) {
-      const int l = lane + C::G * i;
-      if (l < C::NH) {
-        const int m = (l == 0) ? 0 : C::N - l;
-        const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
-        st2(U + (long long)y1 * C::NH + l, cx{0.5f * (ar + br), 0.5f * (ai - bi)});
-        if (has2) st2(U + (long long)y2 * C::NH + l, cx{0.5f * (ai + bi), 0.5f * (br - ar)});
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int x = N2 * j1 + lane;
+        float e1 = 0.f, e2 = 0.f;
+        if (ok && x < p.W) e1 = bld1(rdu, v1, N2 * j1 * 4);
+        if (has2 && x < p.W) e2 = bld1(rdu, v2, N2 * j1 * 4);
+        a[j1] = {e1, e2};
+        rs += e1 + e2;
       }
     }
+    lsum += double(rs);
+    fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < C::NI; ++i) {
+        const int l = lane + C::G * i;
+        if (l < C::NH) {
+          const int m = (l == 0) ? 0 : C::N - l;
+          const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
+          bst2(rU, 0.5f * (ar + br), 0.5f * (ai - bi), (y1 * C::NHP + lane) * 8, C::G * i * 8);
+          if (has2)
+            bst2(rU, 0.5f * (ai + bi), 0.5f * (br - ar), (y2 * C::NHP + lane) * 8, C::G * i * 8);
+        }
+      }
+    }
+    slot_sync();
   }
+  s_sum[threadIdx.x] = lsum;
+  __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int i = 0; i < SLOTS * C::G; ++i) t += s_sum[i];
@@ -286,20 +336,26 @@ k_row_binv(RowBwdInvArgs p) {
   const int strip = blockIdx.x * SLOTS + slot;
   const bool strip_ok = strip < p.nstrips;
   const int y0 = strip * p.strip;
-  const f2* __restrict__ Wv = p.Wv + b * p.img_w;
-  const f2* __restrict__ SD = p.SD + b * p.img_sd;
-  float* __restrict__ gxo = p.dgx + b * p.img_out;
-  float* __restrict__ gyo = p.dgy + b * p.img_out;
-  const int Kb1 = p.Kb + 1;
+  const int Kb1 = p.KbP;
+  const rsrc_t rW = make_buf(p.Wv + b * p.img_w, p.img_w * 8);
+  const rsrc_t rSD = make_buf(p.SD + b * p.img_sd, p.img_sd * 8);
+  const rsrc_t rgx = make_buf(p.dgx + b * p.img_out, p.img_out * 4);
+  const rsrc_t rgy = make_buf(p.dgy + b * p.img_out, p.img_out * 4);
+  const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
+  const rsrc_t rsxm = make_buf(p.sxm, (long long)C::NH * 8);
 
   cx cur[C::NI];
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) {
     const int l = lane + C::G * i;
     cur[i] = {0.f, 0.f};
-    if (strip_ok && l < C::NH && y0 < p.H) cur[i] = ld2(Wv + (long long)y0 * C::NH + l);
+    if (strip_ok && l < C::NH && y0 < p.H) {
+      const f2b v = bld2(rW, (y0 * C::NHP + lane) * 8, C::G * i * 8);
+      cur[i] = {v.x, v.y};
+    }
   }
   for (int it = 0; it < p.strip; ++it) {
+    const int tz = fresh_zero();
     const int y = y0 + it;
     const bool row_ok = strip_ok && y < p.H;
 #pragma unroll
@@ -307,11 +363,19 @@ k_row_binv(RowBwdInvArgs p) {
       const int l = lane + C::G * i;
       if (l < C::NH) {
         cx nxt = {0.f, 0.f};
-        if (row_ok) nxt = ld2(Wv + (long long)(y + 1) * C::NH + l);
-        const cx X1 = cmul(ld2(p.sxm + l), cur[i]);
+        if (row_ok) {
+          const f2b v = bld2(rW, ((y + 1) * C::NHP + lane) * 8, C::G * i * 8);
+          nxt = {v.x, v.y};
+        }
+        const f2b sm = bld2(rsxm, lane * 8, tz + C::G * i * 8);
+        const cx X1 = cmul(cx{sm.x, sm.y}, cur[i]);
         cx X2;
         if (l <= p.Kb) {
-          X2 = row_ok ? ld2(SD + (long long)y * Kb1 + l) : cx{0.f, 0.f};
+          X2 = {0.f, 0.f};
+          if (row_ok) {
+            const f2b v = bld2(rSD, (y * Kb1 + lane) * 8, C::G * i * 8);
+            X2 = {v.x, v.y};
+          }
         } else {
           X2 = csub(cur[i], nxt);
         }
@@ -325,48 +389,51 @@ k_row_binv(RowBwdInvArgs p) {
         cur[i] = nxt;
       }
     }
-    __syncthreads();
+    slot_sync();
     cx bz[N2];
     if (lane < N1) {
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) bz[k2] = {re[lane + N1 * k2], im[lane + N1 * k2]};
     }
-    __syncthreads();
+    slot_sync();
     cx a[N1];
-    inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, p.twB);
+    inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
     if (lane < N2 && row_ok) {
+      const int vo = (y * p.W + lane) * 4;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
         const int x = lane + N2 * j1;
         if (x < p.W) {
-          gxo[(long long)y * p.W + x] = a[j1].x;
-          gyo[(long long)y * p.W + x] = a[j1].y;
+          bst1(rgx, a[j1].x, vo, N2 * j1 * 4);
+          bst1(rgy, a[j1].y, vo, N2 * j1 * 4);
         }
       }
     }
-    __syncthreads();
+    slot_sync();
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// launchers and the table of compiled lengths
+// launchers
 
 template <int N1, int N2>
 struct RowLaunch {
   using C = RowCfg<N1, N2>;
-  static constexpr int SLOTS = (C::G == 64) ? 4 : (256 / C::G);
+  static constexpr int SLOTS = 256 / C::G;
   static hipError_t fwd(const RowFwdArgs& a, int B, hipStream_t s) {
     dim3 grid((a.nstrips + SLOTS - 1) / SLOTS, B);
     hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t inv(const RowInvArgs& a, int B, hipStream_t s) {
-    dim3 grid((a.npairs + SLOTS - 1) / SLOTS, B);
+    const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
+    dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
     hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t bfwd(const RowBwdFwdArgs& a, int B, hipStream_t s) {
-    dim3 grid((a.npairs + SLOTS - 1) / SLOTS, B);
+    const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
+    dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
     hipLaunchKernelGGL((k_row_bfwd<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
