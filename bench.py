@@ -54,8 +54,8 @@ def stage_model(H, W, N, K, Kb, kind):
 
 
 def load_traffic(kernel: str):
-    """HBM bytes per launch measured by rocprofv3 PMC runs (profiles/traffic.json), or None
-    when absent or taken on different kernel sources."""
+    """HBM bytes per image of one pass, from rocprofv3 PMC runs over a batch
+    (profiles/traffic.json), or None when absent or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -65,22 +65,60 @@ def load_traffic(kernel: str):
     if t.get("source_hash") != kernel_source_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
-    if not k:
+    if not k or not t.get("batch"):
         return None
-    return k.get("fetch_bytes", 0) + k.get("write_bytes", 0)
+    return (k.get("fetch_bytes", 0) + k.get("write_bytes", 0)) / t["batch"]
 
 
-def cpu_baseline(w, budget_s=12.0, max_images=30):
+def cpu_baseline(w, budget_s=15.0):
+    """The float64 oracle on a bounded sample: images of the batch in order (cycling if the
+    budget outlasts it), one solve at a time, until budget_s of wall time has passed."""
     import oracle as O
     n = 0
     t0 = time.perf_counter()
-    while n < max_images and (n < 2 or time.perf_counter() - t0 < budget_s):
-        O.solve_fft(w.gx[n], w.gy[n], w.M, w.N)
+    while n < 2 or time.perf_counter() - t0 < budget_s:
+        i = n % w.B
+        O.solve_fft(w.gx[i], w.gy[i], w.M, w.N)
         n += 1
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "solves/s", "cores": O.cpu_workers(), "kind": "oracle",
-            "sample": f"{n} images of the 801x1200 batch on the 1620x2400 torus, float64 "
-                      f"scipy.fft oracle, one image at a time ({dt:.1f} s)"}
+            "sample": f"{n} solves of the 801x1200 images (batch order, cycling) on the 1620x2400 "
+                      f"torus, float64 scipy.fft oracle, one image at a time, {dt:.1f} s"}
+
+
+def pmc_summarize(fetch_csv, write_csv, out_path, batch=100):
+    """Turn two rocprofv3 --pmc runs of `bench.py --pmc-pass` (FETCH_SIZE, then WRITE_SIZE;
+    KiB per dispatch) into HBM bytes per launch of each GFC kernel. Each counter is scaled by
+    what it reads for the 256 MiB device copy in the same run."""
+    import csv
+
+    def read(path, counter):
+        rows = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+        return rows
+
+    copy_bytes = float(64 << 20) * 4
+    out = {"source_hash": kernel_source_hash(), "batch": batch, "kernels": {}, "scale": {}}
+    for key, path, counter in (("fetch_bytes", fetch_csv, "FETCH_SIZE"),
+                               ("write_bytes", write_csv, "WRITE_SIZE")):
+        rows = read(path, counter)
+        cp = [v for k, v in rows if "copyBuffer" in k]
+        if not cp:
+            raise SystemExit(f"{path}: no device copy dispatch to scale {counter} by")
+        scale = copy_bytes / cp[0]
+        out["scale"][counter] = scale
+        for k, v in rows:
+            if "gfc::" not in k:
+                continue
+            name = k.split("gfc::", 1)[1].split("<", 1)[0].split("(", 1)[0]
+            ent = out["kernels"].setdefault(name, {"fetch_bytes": 0.0, "write_bytes": 0.0})
+            ent[key] += v * scale
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -91,10 +129,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--batch", type=int, default=100)
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two counter runs of --pmc-pass")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for rocprofv3 counter runs: one 256 MiB device copy (the scale "
                          "reference for byte counters), one forward and one backward step")
     args = ap.parse_args()
+    if args.pmc_summarize:
+        pmc_summarize(*args.pmc_summarize, os.path.join(ROOT, "profiles", "traffic.json"))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs the solve on a single MI355X "
               "(the batch shards by image across GPUs with no exchange; see DESIGN.md).",

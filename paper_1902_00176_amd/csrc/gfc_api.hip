@@ -19,7 +19,7 @@ constexpr int kLowColsB = 64;   // backward: columns l <= Kb take -D_y inside th
 // Launch geometry defaults; each can be changed per plan with gfc_plan_set_param.
 constexpr int kRowStrip = 16;     // "row_strip": rows per slot in the strip-ordered row passes
 constexpr int kColC = 16;         // "col_c": columns per workgroup in the column pass
-constexpr int kColRows = 32;      // "col_rows": most rows per thread in the column pass (16|32)
+constexpr int kColRows = 32;      // "col_rows": rows per thread in the column pass (16|32)
 constexpr int kPairsPerSlot = 1;  // "row_ppw": row pairs per slot in the pair-ordered passes
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -45,16 +45,18 @@ void cs2pi(long e, long n, double& c, double& s) {
   s = std::sin(t);
 }
 
-struct ColGeom {
-  int C, nseg, Lseg, Llast;
-};
-
-ColGeom col_geometry(int R, int rows_max, int C_req) {
+// Segments of exactly Lseg rows; the block is widened to nseg * Lseg rows when those rows
+// and the reference row r0 still fall in the zero part of the torus, else the last
+// segment is shorter (tail).
+ColGeom col_geometry(int R, int M, int r0, int rows, int C_req) {
   ColGeom g;
-  int nseg = (R + rows_max - 1) / rows_max;
-  g.Lseg = (R + nseg - 1) / nseg;
-  g.nseg = (R + g.Lseg - 1) / g.Lseg;
-  g.Llast = R - (g.nseg - 1) * g.Lseg;
+  if ((R + rows - 1) / rows > kColMaxThreads) rows = 32;
+  g.Lseg = rows;
+  g.nseg = (R + rows - 1) / rows;
+  const int Rp = g.nseg * rows;
+  g.tail = !(Rp < M && r0 >= Rp);
+  g.Rp = g.tail ? R : Rp;
+  g.Llast = g.Rp - (g.nseg - 1) * rows;
   int C = C_req;
   while (C > 1 && C * g.nseg > kColMaxThreads) C /= 2;
   g.C = C;
@@ -80,8 +82,9 @@ struct gfc_plan_s {
 
 namespace {
 
-void fill_colconst(const gfc_plan_s& p, int R, const ColGeom& g, bool forward,
+void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
                    std::vector<ColConst>& out) {
+  const int R = g.Rp;
   out.assign(p.NH, ColConst{});
   const double M = p.M, N = p.N;
   for (int l = 0; l < p.NH; ++l) {
@@ -90,6 +93,7 @@ void fill_colconst(const gfc_plan_s& p, int R, const ColGeom& g, bool forward,
       k.rho = 1.0;
       k.inv_rho = 1.0;
       k.outs = 1.0 / N;
+      k.kseg = g.nseg;
       out[l] = k;
       continue;
     }
@@ -109,6 +113,10 @@ void fill_colconst(const gfc_plan_s& p, int R, const ColGeom& g, bool forward,
     k.outs = -rho / N;
     k.rhoL = pw(g.Lseg);
     k.rhoLl = pw(g.Llast);
+    // rho^d < 2^-64 for d >= dmax rows; carries from further than that are dropped
+    const double dmax = std::ceil(64.0 * std::log(2.0) / -lr);
+    const double ks = std::ceil(dmax / g.Lseg) + 1.0;
+    k.kseg = ks >= double(g.nseg) ? g.nseg : int(ks);
     k.gL = one_minus_pw(2.0 * g.Lseg) / one_m_r2;
     k.gLl = one_minus_pw(2.0 * g.Llast) / one_m_r2;
     k.cg = pw(M - R + 1) * inv1mrM;
@@ -135,8 +143,8 @@ gfc_status hip_status(hipError_t e) { return e == hipSuccess ? GFC_OK : GFC_E_HI
 
 // launch geometry that follows from the sizes and the tunable parameters
 void derive_geometry(gfc_plan_s* p) {
-  p->gf = col_geometry(p->H + 1, p->col_rows, p->col_c);
-  p->gb = col_geometry(p->H, p->col_rows, p->col_c);
+  p->gf = col_geometry(p->H + 1, p->M, p->r0, p->col_rows, p->col_c);
+  p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows, p->col_c);
   p->nstrips_f = (p->H + 1 + p->row_strip - 1) / p->row_strip;
   p->nstrips_b = (p->H + p->row_strip - 1) / p->row_strip;
   p->npairs = (p->H + 1) / 2;
@@ -169,7 +177,8 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
   if (!out) return GFC_E_ARG;
   *out = nullptr;
   if (H < 1 || W < 1 || M < 0 || N < 0 || flags != GFC_FLAG_NONE) return GFC_E_ARG;
-  if (H > (1 << 15) || W > (1 << 15)) return GFC_E_SIZE;
+  // the column pass holds a whole column in one workgroup: at most 1024 segments of 32 rows
+  if (H >= (1 << 15) || W > (1 << 15)) return GFC_E_SIZE;
   if (M == 0) M = smooth_at_least(2L * H);
   if (N == 0) N = smooth_at_least(2L * W);
   if (M < H + 2 || N < W + 2) return GFC_E_SIZE;
@@ -266,8 +275,8 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
     dsh[l] = f2{float(c), float(-s)};    // e^{-2 pi i l c0 / N}
   }
   std::vector<ColConst> ccf, ccb;
-  fill_colconst(*p, p->H + 1, p->gf, true, ccf);
-  fill_colconst(*p, p->H, p->gb, false, ccb);
+  fill_colconst(*p, p->gf, true, ccf);
+  fill_colconst(*p, p->gb, false, ccb);
 
   size_t off = 0;
   const size_t o_twA = off; off = align256(off + twA.size() * sizeof(f2));
@@ -390,6 +399,8 @@ gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const
     c.nseg = p->gf.nseg;
     c.Lseg = p->gf.Lseg;
     c.Llast = p->gf.Llast;
+    c.Rp = p->gf.Rp;
+    c.nparts = p->ntiles_f;
     c.img_t = img_t;
     c.img_sb = img_sb;
     const gfc_status st = hip_status(launch_col_fwd(c, B, s));
@@ -475,6 +486,7 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     c.nseg = p->gb.nseg;
     c.Lseg = p->gb.Lseg;
     c.Llast = p->gb.Llast;
+    c.Rp = p->gb.Rp;
     c.img_t = img_t;
     c.img_sd = img_sd;
     const gfc_status st = hip_status(launch_col_bwd(c, B, s));

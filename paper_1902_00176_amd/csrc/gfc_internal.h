@@ -89,28 +89,41 @@ struct ColConst {
   double ra, rb;    // forward: z[r0] = ra * w[R-1] + rb * z[0]
   double cgd, cTd;  // backward: Dirac at r0 terms
   double wre, wim;  // forward: reference term = wre * Re(z[r0]) - wim * Im(z[r0])
+  int kseg;         // segments over which rho^distance stays above 2^-64 (capped at nseg)
+  int pad_;
+};
+
+// Column geometry. A column of R input rows is cut into nseg segments of Lseg rows (one
+// thread each), the last one Llast rows long. When the zero rows of the torus allow it the
+// block is treated as Rp = nseg * Lseg rows (the extra rows are zeros of the torus that
+// read as 0 past the end of the buffer), so every segment is full; otherwise (tail) Rp = R.
+// All recursion constants use Rp.
+struct ColGeom {
+  int C, nseg, Lseg, Llast, Rp;
+  bool tail;
 };
 
 struct ColFwdArgs {
-  f2* T;              // in: T1 [B][H+1][NH]; out (in place): T2 rows [0, H)
-  const f2* SB;       // [B][H][K+1]
+  f2* T;              // in: T1 [B][H+1][NHP]; out (in place): T2 rows [0, H)
+  const f2* SB;       // [B][H][KP]
   const ColConst* cc; // [NH]
-  double* partial;    // [B][ntiles]
-  int ntiles, tile0;  // column tiles in all; first tile of this launch (set by the launcher)
+  double* partial;    // [B][nparts]: per column-tile sums of the reference terms
+  int nparts;         // column tiles
+  int tile0;          // first tile of this launch (set by the launcher)
   int H, M, NH, NHP, K, KP, r0;
-  int C, nseg, Lseg, Llast;   // R = H + 1 rows of input
+  int C, nseg, Lseg, Llast, Rp;   // R = H + 1 rows of input
   long long img_t, img_sb;
 };
 
 struct ColBwdArgs {
-  f2* T;              // in: U [B][H][NH] (row stride NH); out: W rows [0, H]
-  f2* SD;             // out: [B][H][Kb+1]
+  f2* T;              // in: U [B][H+1][NHP] rows [0, H); out: W rows [0, H]
+  f2* SD;             // out: [B][H][KbP]
   const ColConst* cc; // [NH]
   const double* sums; // [B][nsums]: sum(du) = sum of the partials
   const f2* dshift;   // [NH]: w_N^(l c0) (forward sign): row DFT of a Dirac at column c0
   int nsums;
   int H, M, NH, NHP, Kb, KbP, r0;
-  int C, nseg, Lseg, Llast;   // R = H rows of input
+  int C, nseg, Lseg, Llast, Rp;   // R = H rows of input
   long long img_t, img_sd;
 };
 
@@ -128,6 +141,6 @@ const RowKernels* row_kernel_at(int i);
 
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s);
 hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
-constexpr int kColMaxThreads = 512;  // largest column-pass workgroup
+constexpr int kColMaxThreads = 1024;  // largest column-pass workgroup
 
 }  // namespace gfc
