@@ -121,6 +121,49 @@ def pmc_summarize(fetch_csv, write_csv, out_path, batch=100):
     print(json.dumps(out), flush=True)
 
 
+def ragged_bench(torch, gfc, synth, dev, stream, reps):
+    """The uneven-size batch (200 images, H, W ~ U{64..1024}, default tori): one ragged
+    solve (graph replay) against the plain path, one single-image solve per image on the
+    same stream. Both produce identical outputs."""
+    import statistics
+    sizes = synth.ragged_sizes()
+    pairs = synth.make_ragged(sizes=sizes)
+    r = gfc.Ragged(sizes).build(dev)
+    gx = r.pack([p[0] for p in pairs], dev)
+    gy = r.pack([p[1] for p in pairs], dev)
+    u = torch.empty_like(gx)
+    ws = torch.empty(r.workspace_size(), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        for _ in range(3):
+            fn(gx, gy, out=u, workspace=ws)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(gx, gy, out=u, workspace=ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    ms_r = timed(r.solve)
+    ms_p = timed(r.solve_sequential)
+    pbytes = 0.0
+    for H, W, M, N in r.sizes:
+        NH = N // 2 + 1
+        pbytes += 12.0 * H * W + 4 * 8.0 * (H + 1) * NH + 2 * 2 * 8.0 * (H + 1) * 17
+    B = len(sizes)
+    return {"workload": "ragged200_64to1024", "images": B,
+            "distinct_row_lengths": len({s[3] for s in r.sizes}),
+            "ragged_solves_per_s": B / (ms_r / 1e3), "ragged_ms": ms_r,
+            "plain_solves_per_s": B / (ms_p / 1e3), "plain_ms": ms_p,
+            "ragged_over_plain": ms_p / ms_r,
+            "ragged_hbm_frac": pbytes / (ms_r / 1e3) / HBM_PEAK}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +171,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two counter runs of --pmc-pass")
@@ -283,6 +327,9 @@ def main():
                              "stages_ms": {k: round(v, 5) for k, v in bms.items()},
                              "bwd_hbm_frac": sum(v[0] for v in mb.values()) * B /
                              (sum(bms.values()) / 1e3) / HBM_PEAK}
+
+    if not args.no_ragged:
+        result["ragged"] = ragged_bench(torch, gfc, synth, dev, stream, max(args.steps // 2, 3))
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w)

@@ -48,7 +48,7 @@ typedef enum {
   GFC_E_NOT_BUILT = 3,  /* gfc_green_build has not run on this plan                      */
   GFC_E_WORKSPACE = 4,  /* workspace smaller than gfc_workspace_size()                   */
   GFC_E_HIP = 5,        /* a HIP runtime call or an earlier asynchronous kernel failed   */
-  GFC_E_OOM = 6         /* device allocation of plan tables failed                       */
+  GFC_E_OOM = 6         /* device allocation of plan or schedule tables failed           */
 } gfc_status;
 
 /* Plan flags. */
@@ -71,12 +71,13 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
 gfc_status gfc_green_build(gfc_plan_t p, void* stream);
 
 /*
- * Launch geometry of a plan (results do not depend on it; only speed does). Call before
+ * Launch geometry of a plan (speed depends on it; results only through the summation
+ * order of the float64 reference term over column tiles, "col_c"). Call before
  * gfc_green_build; GFC_E_ARG for an unknown name, a value out of range, or a built plan.
  *   "row_strip" 1..256  rows handled by one FFT slot in the strip-ordered row passes
  *   "row_ppw"   1..64   row pairs handled by one FFT slot in the pair-ordered row passes
  *   "col_c"     1..64   (power of two) columns per workgroup in the column pass
- *   "col_rows"  16|32   most rows per thread in the column pass
+ *   "col_rows"  16|32   rows per thread in the column pass
  * The project's autotuner chooses these per (H, W, M, N); host-only.
  */
 gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value);
@@ -131,6 +132,64 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
 gfc_status gfc_green_export(gfc_plan_t p, double* half_spectrum_host);
 
 void gfc_plan_destroy(gfc_plan_t p);
+
+/* ---- ragged batches ---------------------------------------------------------------------
+ * B images of different sizes solved together (each exactly as gfc_solve_batch would solve
+ * it alone on its own torus). Inputs and outputs are PACKED: image i occupies elements
+ * [off[i], off[i+1]) of gx, gy and u, row-major [H_i][W_i], off[0] = 0,
+ * off[i+1] = off[i] + H_i * W_i (gfc_ragged_offsets). A ragged object owns one plan per
+ * distinct image size (float64 tables built once) and a schedule of work items; its
+ * solve replays a HIP graph captured on the first call with given buffer addresses.
+ */
+
+/* gfc_ragged_solve enqueues the passes directly instead of capturing and replaying a graph */
+#define GFC_RAGGED_NO_GRAPH 1u
+
+/*
+ * Create a ragged object for B images: H[i] x W[i] on an M[i] x N[i] torus. M and N may be
+ * NULL (or hold 0 entries) for the default torus of each image; the size rules are those
+ * of gfc_plan_create, whose status is returned for the first image that breaks them.
+ * flags: 0 or GFC_RAGGED_NO_GRAPH. Host-only.
+ */
+gfc_status gfc_ragged_create(gfc_ragged_t* out, int B, const int* H, const int* W,
+                             const int* M, const int* N, unsigned flags);
+
+/*
+ * Build every image plan's float64 tables (as gfc_green_build), the per-image argument
+ * tables and the work-item schedule, and upload them on `stream` (synchronises it once).
+ * Idempotent.
+ */
+gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream);
+
+/* Resolved sizes of image i (any output may be NULL). Host-only. */
+gfc_status gfc_ragged_image(gfc_ragged_t r, int i, int* H, int* W, int* M, int* N);
+
+/* The B + 1 element offsets of the packed layout, written to a HOST array. */
+gfc_status gfc_ragged_offsets(gfc_ragged_t r, int64_t* offsets);
+
+/* Bytes of workspace needed by gfc_ragged_solve (after gfc_ragged_build). */
+gfc_status gfc_ragged_workspace_size(gfc_ragged_t r, size_t* bytes);
+
+/*
+ * Forward solve of all B images (eqs. (3), (22), (23) and Algorithm B per image): gx, gy,
+ * u are packed DEVICE arrays (see above); u must not alias gx or gy. The first call with a
+ * given (gx, gy, u, workspace) captures the launch sequence into a HIP graph; later calls
+ * with the same addresses only launch the graph on `stream`. A call with other addresses
+ * synchronises `stream` once, then captures anew. With GFC_RAGGED_NO_GRAPH every call
+ * enqueues the launches itself. Calls that may overlap need separate ragged objects.
+ */
+gfc_status gfc_ragged_solve(gfc_ragged_t r, const float* gx, const float* gy, float* u,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * The same result by B single-image gfc_solve_batch calls on `stream`, one per image with
+ * its plan (the reference a ragged solve is compared against, and the plain baseline).
+ */
+gfc_status gfc_ragged_solve_sequential(gfc_ragged_t r, const float* gx, const float* gy,
+                                       float* u, void* workspace, size_t ws_bytes,
+                                       void* stream);
+
+void gfc_ragged_destroy(gfc_ragged_t r);
 
 /* 1 if N is a supported row-FFT length, else 0. Host-only. */
 int gfc_supported_length(int N);

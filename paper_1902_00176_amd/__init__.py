@@ -79,18 +79,18 @@ def lib():
 
 
 def _bind_ragged(L):
-    if not hasattr(L, "gfc_ragged_create"):
-        return
     vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     ip = ctypes.POINTER(ctypes.c_int)
-    L.gfc_ragged_create.argtypes = [ctypes.POINTER(vp), i, ip, ip, ctypes.c_uint]
-    L.gfc_ragged_create.restype = ctypes.c_int
+    L.gfc_ragged_create.argtypes = [ctypes.POINTER(vp), i, ip, ip, ip, ip, ctypes.c_uint]
     L.gfc_ragged_build.argtypes = [vp, vp]
-    L.gfc_ragged_build.restype = ctypes.c_int
+    L.gfc_ragged_image.argtypes = [vp, i, ip, ip, ip, ip]
+    L.gfc_ragged_offsets.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.gfc_ragged_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
-    L.gfc_ragged_workspace_size.restype = ctypes.c_int
     L.gfc_ragged_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp]
-    L.gfc_ragged_solve.restype = ctypes.c_int
+    L.gfc_ragged_solve_sequential.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    for name in ("gfc_ragged_create", "gfc_ragged_build", "gfc_ragged_image", "gfc_ragged_offsets",
+                 "gfc_ragged_workspace_size", "gfc_ragged_solve", "gfc_ragged_solve_sequential"):
+        getattr(L, name).restype = ctypes.c_int
     L.gfc_ragged_destroy.argtypes = [vp]
     L.gfc_ragged_destroy.restype = None
 
@@ -300,6 +300,111 @@ def solve(gx, gy, M: int = 0, N: int = 0, **kw):
 def solve_backward(du, M: int = 0, N: int = 0, **kw):
     """(dgx, dgy) = adjoint of the solve applied to du [..., H, W]."""
     return get_plan(du.shape[-2], du.shape[-1], M or 0, N or 0).backward(du, **kw)
+
+
+RAGGED_NO_GRAPH = 1
+
+
+class Ragged:
+    """A ragged batch: images of different sizes solved together (gfc_ragged_*).
+
+    sizes: a list of (H, W) or (H, W, M, N) (M = N = 0: the default torus of that image).
+    Inputs and outputs are packed float32 device tensors: image i occupies
+    [offsets[i], offsets[i+1]) row-major. pack() / unpack() convert from / to lists.
+    """
+
+    def __init__(self, sizes, flags: int = 0):
+        sizes = [tuple(int(v) for v in s) + (0, 0)[:4 - len(s)] for s in sizes]
+        self.B = len(sizes)
+        arr = lambda k: (ctypes.c_int * max(1, self.B))(*[s[k] for s in sizes])
+        h = ctypes.c_void_p()
+        _check(lib().gfc_ragged_create(ctypes.byref(h), self.B, arr(0), arr(1), arr(2), arr(3),
+                                       int(flags)), "gfc_ragged_create")
+        self._h = h
+        self._built_on = None
+        self.sizes = []
+        for k in range(self.B):
+            v = [ctypes.c_int() for _ in range(4)]
+            _check(lib().gfc_ragged_image(h, k, *[ctypes.byref(x) for x in v]), "gfc_ragged_image")
+            self.sizes.append(tuple(x.value for x in v))
+        off = (ctypes.c_int64 * (self.B + 1))()
+        _check(lib().gfc_ragged_offsets(h, off), "gfc_ragged_offsets")
+        self.offsets = np.array(off[:], dtype=np.int64)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gfc_ragged_destroy(h)
+            self._h = None
+
+    def build(self, device=None, stream=None):
+        import torch
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self._built_on is None:
+            with torch.cuda.device(dev):
+                _check(lib().gfc_ragged_build(self._h, _stream_ptr(torch, dev, stream)),
+                       "gfc_ragged_build")
+            self._built_on = dev
+        elif self._built_on != dev:
+            raise ValueError(f"ragged batch built on {self._built_on}, used on {dev}")
+        return self
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().gfc_ragged_workspace_size(self._h, ctypes.byref(n)), "gfc_ragged_workspace_size")
+        return n.value
+
+    def pack(self, arrays, device):
+        """Concatenate a list of [H_i, W_i] arrays/tensors into one packed float32 tensor."""
+        import torch
+        parts = [torch.as_tensor(a, dtype=torch.float32).reshape(-1) for a in arrays]
+        return torch.cat(parts).to(device) if parts else torch.empty(0, device=device)
+
+    def unpack(self, packed):
+        return [packed[self.offsets[k]:self.offsets[k + 1]].view(self.sizes[k][0], self.sizes[k][1])
+                for k in range(self.B)]
+
+    def _run(self, fn, name, gx, gy, out, workspace, stream):
+        import torch
+        dev = gx.device
+        for t in (gx, gy):
+            if t.dtype != torch.float32 or t.device != dev or t.dim() != 1 or not t.is_contiguous():
+                raise TypeError("packed inputs must be contiguous 1-D float32 tensors on one device")
+            if t.numel() != int(self.offsets[-1]):
+                raise ValueError(f"packed inputs must hold {int(self.offsets[-1])} elements")
+        self.build(dev)
+        u = out if out is not None else torch.empty_like(gx)
+        if workspace is None:
+            need = self.workspace_size()
+            if self._ws is None or self._ws.numel() < need or self._ws.device != dev:
+                self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+            workspace = self._ws
+        with torch.cuda.device(dev):
+            _check(fn(self._h, gx.data_ptr(), gy.data_ptr(), u.data_ptr(), workspace.data_ptr(),
+                      workspace.numel() * workspace.element_size(), _stream_ptr(torch, dev, stream)),
+                   name)
+        return u
+
+    def solve(self, gx, gy, out=None, workspace=None, stream=None):
+        """Packed forward solve of every image (one graph replay once captured)."""
+        return self._run(lib().gfc_ragged_solve, "gfc_ragged_solve", gx, gy, out, workspace, stream)
+
+    def solve_sequential(self, gx, gy, out=None, workspace=None, stream=None):
+        """The same result by one single-image plain solve per image."""
+        return self._run(lib().gfc_ragged_solve_sequential, "gfc_ragged_solve_sequential", gx, gy,
+                         out, workspace, stream)
+
+
+def ragged_solve(pairs, device=None):
+    """Solve a list of (gx, gy) pairs of different sizes in one ragged launch; returns the
+    list of u (views into one packed tensor)."""
+    import torch
+    dev = torch.device(device) if device is not None else pairs[0][0].device
+    r = Ragged([tuple(gx.shape[-2:]) for gx, _ in pairs])
+    gx = r.pack([p[0] for p in pairs], dev)
+    gy = r.pack([p[1] for p in pairs], dev)
+    return r.unpack(r.solve(gx, gy))
 
 
 def _make_function():

@@ -8,21 +8,13 @@
 
 #include "../../include/gfc.h"
 #include "gfc_internal.h"
+#include "gfc_plan.h"
 
 using namespace gfc;
 
 namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr int kLowCols = 16;    // forward: columns l <= K use the split (x-spectral) input
-constexpr int kLowColsB = 64;   // backward: columns l <= Kb take -D_y inside the recursion
-// Launch geometry defaults; each can be changed per plan with gfc_plan_set_param.
-constexpr int kRowStrip = 16;     // "row_strip": rows per slot in the strip-ordered row passes
-constexpr int kColC = 16;         // "col_c": columns per workgroup in the column pass
-constexpr int kColRows = 32;      // "col_rows": rows per thread in the column pass (16|32)
-constexpr int kPairsPerSlot = 1;  // "row_ppw": row pairs per slot in the pair-ordered passes
-
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool smooth235(long n) {
   if (n <= 0) return false;
@@ -65,20 +57,6 @@ ColGeom col_geometry(int R, int M, int r0, int rows, int C_req) {
 
 }  // namespace
 
-struct gfc_plan_s {
-  int H = 0, W = 0, M = 0, N = 0, NH = 0, NHP = 0, KP = 0, KbP = 0, oy = 0, ox = 0, r0 = 0, c0 = 0, K = 0, Kb = 0;
-  unsigned flags = 0;
-  const RowKernels* rk = nullptr;
-  ColGeom gf{}, gb{};
-  int row_strip = kRowStrip, row_ppw = kPairsPerSlot, col_c = kColC, col_rows = kColRows;
-  int nstrips_f = 0, nstrips_b = 0, npairs = 0;
-  int ntiles_f = 0, ntiles_b = 0, nsums = 0;
-  bool built = false;
-  int device = -1;
-  void* dmem = nullptr;
-  f2 *twA = nullptr, *twB = nullptr, *sx = nullptr, *sxm = nullptr, *dshift = nullptr;
-  ColConst *ccf = nullptr, *ccb = nullptr;
-};
 
 namespace {
 
@@ -139,7 +117,6 @@ void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
   }
 }
 
-gfc_status hip_status(hipError_t e) { return e == hipSuccess ? GFC_OK : GFC_E_HIP; }
 
 // launch geometry that follows from the sizes and the tunable parameters
 void derive_geometry(gfc_plan_s* p) {
@@ -317,26 +294,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   return GFC_OK;
 }
 
-namespace {
-struct WsLayout {
-  size_t t, side, red, total;
-};
-WsLayout ws_layout(const gfc_plan_s* p, int B) {
-  WsLayout w{};
-  const size_t Bz = size_t(B);
-  const size_t tbytes = Bz * size_t(p->H + 1) * p->NHP * sizeof(f2);
-  const size_t sb = Bz * size_t(p->H) * p->KP * sizeof(f2);
-  const size_t sd = Bz * size_t(p->H) * p->KbP * sizeof(f2);
-  const size_t pf = Bz * size_t(p->ntiles_f) * sizeof(double);
-  const size_t ps = Bz * size_t(p->nsums) * sizeof(double);
-  w.t = 0;
-  w.side = align256(tbytes);
-  w.red = w.side + align256(std::max(sb, sd));
-  w.total = w.red + align256(std::max(pf, ps));
-  return w;
-}
-}  // namespace
-
 gfc_status gfc_workspace_size(gfc_plan_t p, int B, size_t* bytes) {
   if (!p || !bytes || B < 0) return GFC_E_ARG;
   *bytes = ws_layout(p, B).total;
@@ -359,67 +316,17 @@ gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const
   f2* SB = reinterpret_cast<f2*>(ws + w.side);
   double* partial = reinterpret_cast<double*>(ws + w.red);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const long long img_t = (long long)(p->H + 1) * p->NHP;
-  const long long img_sb = (long long)p->H * p->KP;
 
   if (stage == 0 || stage == 1) {
-    RowFwdArgs a{};
-    a.gx = gx;
-    a.gy = gy;
-    a.T1 = T;
-    a.SB = SB;
-    a.twA = p->twA;
-    a.sx = p->sx;
-    a.H = p->H;
-    a.W = p->W;
-    a.K = p->K;
-    a.KP = p->KP;
-    a.strip = p->row_strip;
-    a.nstrips = p->nstrips_f;
-    a.img_in = (long long)p->H * p->W;
-    a.img_t1 = img_t;
-    a.img_sb = img_sb;
-    const gfc_status st = hip_status(p->rk->fwd(a, B, s));
+    const gfc_status st = hip_status(p->rk->fwd(row_fwd_args(p, gx, gy, T, SB), B, s));
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 2) {
-    ColFwdArgs c{};
-    c.T = T;
-    c.SB = SB;
-    c.cc = p->ccf;
-    c.partial = partial;
-    c.H = p->H;
-    c.M = p->M;
-    c.NH = p->NH;
-    c.NHP = p->NHP;
-    c.K = p->K;
-    c.KP = p->KP;
-    c.r0 = p->r0;
-    c.C = p->gf.C;
-    c.nseg = p->gf.nseg;
-    c.Lseg = p->gf.Lseg;
-    c.Llast = p->gf.Llast;
-    c.Rp = p->gf.Rp;
-    c.nparts = p->ntiles_f;
-    c.img_t = img_t;
-    c.img_sb = img_sb;
-    const gfc_status st = hip_status(launch_col_fwd(c, B, s));
+    const gfc_status st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s));
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 3) {
-    RowInvArgs v{};
-    v.T2 = T;
-    v.u = u;
-    v.partial = partial;
-    v.nparts = p->ntiles_f;
-    v.twB = p->twB;
-    v.H = p->H;
-    v.W = p->W;
-    v.npairs = (p->H + 1) / 2;
-    v.ppw = p->row_ppw;
-    v.img_t2 = img_t;
-    v.img_u = (long long)p->H * p->W;
-    const gfc_status st = hip_status(p->rk->inv(v, B, s));
+    const gfc_status st = hip_status(p->rk->inv(row_inv_args(p, T, u, partial), B, s));
     if (st != GFC_OK) return st;
   }
   return GFC_OK;

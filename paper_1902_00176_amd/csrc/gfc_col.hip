@@ -270,6 +270,22 @@ __global__ void __launch_bounds__(kColMaxThreads) k_col_fwd(ColFwdArgs p) {
                                     s_mem + p.nseg * p.C);
 }
 
+// ragged batches: one (image, tile) work item per workgroup, the image's arguments from a
+// table with workspace addresses as offsets; the workgroup shape is the largest over the
+// images (threads past an image's C * nseg idle through the barriers)
+template <int LMAX, bool LOWTILE, bool TAIL>
+__global__ void __launch_bounds__(kColMaxThreads)
+k_col_fwd_rg(RgBase base, const RgCol* tab, const RgItem* items) {
+  extern __shared__ dc s_mem[];
+  const RgItem it = items[blockIdx.x];
+  const RgCol& e = tab[it.img];
+  ColFwdArgs p = e.a;
+  p.T = reinterpret_cast<f2*>(base.ws + e.t);
+  p.SB = reinterpret_cast<const f2*>(base.ws + e.side);
+  p.partial = reinterpret_cast<double*>(base.ws + e.red);
+  col_fwd_tile<LMAX, LOWTILE, TAIL>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+}
+
 // ---------------------------------------------------------------------------------------
 // Backward: input rows [0, R), R = H, plus a Dirac of weight dv = -sum(du) w_N^(l c0) at
 // row r0 (the adjoint of the reference-pixel subtraction). Outputs w rows [0, H] and, for
@@ -491,6 +507,35 @@ hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s) {
   } else if (a.Lseg == 32) {
     if (tail) launch_fwd_tiles<32, true>(a, ntiles, nlow, B, shm, s);
     else launch_fwd_tiles<32, false>(a, ntiles, nlow, B, shm, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+namespace {
+template <int LMAX, bool TAIL>
+void launch_rg_tiles(const RgBase& base, const RgCol* tab, const RgItem* low, int nlow,
+                     const RgItem* rest, int nrest, int threads, size_t shm, hipStream_t s) {
+  if (nlow > 0)
+    hipLaunchKernelGGL((k_col_fwd_rg<LMAX, true, TAIL>), dim3(nlow), dim3(threads), shm, s,
+                       base, tab, low);
+  if (nrest > 0)
+    hipLaunchKernelGGL((k_col_fwd_rg<LMAX, false, TAIL>), dim3(nrest), dim3(threads), shm, s,
+                       base, tab, rest);
+}
+}  // namespace
+
+hipError_t launch_col_fwd_rg(const RgBase& base, const RgCol* tab, const RgItem* low,
+                             int nlow, const RgItem* rest, int nrest, int Lseg, bool tail,
+                             int threads, size_t shm, hipStream_t s) {
+  if (threads < 64 || threads > kColMaxThreads || threads % 64) return hipErrorInvalidValue;
+  if (Lseg == 16) {
+    if (tail) launch_rg_tiles<16, true>(base, tab, low, nlow, rest, nrest, threads, shm, s);
+    else launch_rg_tiles<16, false>(base, tab, low, nlow, rest, nrest, threads, shm, s);
+  } else if (Lseg == 32) {
+    if (tail) launch_rg_tiles<32, true>(base, tab, low, nlow, rest, nrest, threads, shm, s);
+    else launch_rg_tiles<32, false>(base, tab, low, nlow, rest, nrest, threads, shm, s);
   } else {
     return hipErrorInvalidValue;
   }

@@ -127,6 +127,33 @@ struct ColBwdArgs {
   long long img_t, img_sd;
 };
 
+// ---- ragged batches ---------------------------------------------------------------------
+// One launch covers many images of different sizes: each workgroup takes one work item
+// (image, block of that image's grid) and the image's argument block from a table built
+// once on the host. Buffer addresses in the tables are offsets from the bases passed at
+// launch: input/output elements, workspace bytes.
+struct RgItem {
+  int img, blk;
+};
+struct RgBase {
+  const float* gx;
+  const float* gy;
+  float* u;
+  unsigned char* ws;
+};
+struct RgRowFwd {
+  RowFwdArgs a;
+  long long in, t, side;
+};
+struct RgCol {
+  ColFwdArgs a;
+  long long t, side, red;
+};
+struct RgRowInv {
+  RowInvArgs a;
+  long long out, t, red;
+};
+
 // launchers (defined in the kernel files)
 struct RowKernels {
   int N, N1, N2, G, slots;
@@ -134,6 +161,8 @@ struct RowKernels {
   hipError_t (*inv)(const RowInvArgs&, int B, hipStream_t);
   hipError_t (*bfwd)(const RowBwdFwdArgs&, int B, hipStream_t);
   hipError_t (*binv)(const RowBwdInvArgs&, int B, hipStream_t);
+  hipError_t (*rg_fwd)(const RgBase&, const RgRowFwd*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*rg_inv)(const RgBase&, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
 };
 const RowKernels* find_row_kernels(int N);
 int row_kernel_count();
@@ -141,6 +170,11 @@ const RowKernels* row_kernel_at(int i);
 
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s);
 hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
+// ragged forward column pass: items of tiles holding columns l <= K and of the others,
+// one workgroup shape (threads, LDS bytes) for all images, rows per segment Lseg
+hipError_t launch_col_fwd_rg(const RgBase& base, const RgCol* tab, const RgItem* low,
+                             int nlow, const RgItem* rest, int nrest, int Lseg, bool tail,
+                             int threads, size_t shm, hipStream_t s);
 constexpr int kColMaxThreads = 1024;  // largest column-pass workgroup
 
 }  // namespace gfc

@@ -122,9 +122,9 @@ __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], floa
 // ---------------------------------------------------------------------------------------
 // Forward row pass (divergence + row R2C, eq. (3) and the row half of F(L) in eq. (23)).
 // Rows of the block are processed in strips so the previous row's Ey^ stays in registers.
+// bx: block of SLOTS strips; b: image of the batch.
 template <int N1, int N2, int SLOTS>
-__global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_fwd(RowFwdArgs p) {
+__device__ __forceinline__ void row_fwd_body(const RowFwdArgs& p, int bx, int b) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
@@ -132,8 +132,7 @@ k_row_fwd(RowFwdArgs p) {
   const int lane = threadIdx.x % C::G;
   float* re = s_re[slot];
   float* im = s_im[slot];
-  const int b = blockIdx.y;
-  const int strip = blockIdx.x * SLOTS + slot;
+  const int strip = bx * SLOTS + slot;
   const bool strip_ok = strip < p.nstrips;
   const int y0 = strip * p.strip;
   const int K1 = p.KP;
@@ -192,12 +191,31 @@ k_row_fwd(RowFwdArgs p) {
   }
 }
 
+template <int N1, int N2, int SLOTS>
+__global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
+k_row_fwd(RowFwdArgs p) {
+  row_fwd_body<N1, N2, SLOTS>(p, blockIdx.x, blockIdx.y);
+}
+
+// ragged batches: one work item (image, block) per workgroup; pointers rebased per image
+template <int N1, int N2, int SLOTS>
+__global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
+k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
+  const RgItem it = items[blockIdx.x];
+  const RgRowFwd& e = tab[it.img];
+  RowFwdArgs p = e.a;
+  p.gx = base.gx + e.in;
+  p.gy = base.gy + e.in;
+  p.T1 = reinterpret_cast<f2*>(base.ws + e.t);
+  p.SB = reinterpret_cast<f2*>(base.ws + e.side);
+  row_fwd_body<N1, N2, SLOTS>(p, it.blk, 0);
+}
+
 // ---------------------------------------------------------------------------------------
 // Inverse row pass (row C2R of eq. (23), real part, crop and Algorithm B's constant).
 // Each slot handles p.ppw pairs of rows, two rows per complex inverse FFT.
 template <int N1, int N2, int SLOTS>
-__global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_inv(RowInvArgs p) {
+__device__ __forceinline__ void row_inv_body(const RowInvArgs& p, int bx, int b) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
@@ -205,7 +223,6 @@ k_row_inv(RowInvArgs p) {
   const int lane = threadIdx.x % C::G;
   float* re = s_re[slot];
   float* im = s_im[slot];
-  const int b = blockIdx.y;
   const rsrc_t rT2 = make_buf(p.T2 + b * p.img_t2, p.img_t2 * 8);
   const rsrc_t ru = make_buf(p.u + b * p.img_u, p.img_u * 4);
   const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
@@ -220,7 +237,7 @@ k_row_inv(RowInvArgs p) {
 
   for (int r = 0; r < p.ppw; ++r) {
     const int tz = fresh_zero();
-    const int q = (blockIdx.x * SLOTS + slot) * p.ppw + r;
+    const int q = (bx * SLOTS + slot) * p.ppw + r;
     const bool ok = q < p.npairs;
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
@@ -252,6 +269,24 @@ k_row_inv(RowInvArgs p) {
     }
     slot_sync();
   }
+}
+
+template <int N1, int N2, int SLOTS>
+__global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
+k_row_inv(RowInvArgs p) {
+  row_inv_body<N1, N2, SLOTS>(p, blockIdx.x, blockIdx.y);
+}
+
+template <int N1, int N2, int SLOTS>
+__global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
+k_row_inv_rg(RgBase base, const RgRowInv* tab, const RgItem* items) {
+  const RgItem it = items[blockIdx.x];
+  const RgRowInv& e = tab[it.img];
+  RowInvArgs p = e.a;
+  p.T2 = reinterpret_cast<const f2*>(base.ws + e.t);
+  p.u = base.u + e.out;
+  p.partial = reinterpret_cast<const double*>(base.ws + e.red);
+  row_inv_body<N1, N2, SLOTS>(p, it.blk, 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -442,11 +477,23 @@ struct RowLaunch {
     hipLaunchKernelGGL((k_row_binv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
+  static hipError_t rg_fwd(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+                           int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_fwd_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
+                       base, tab, items);
+    return hipGetLastError();
+  }
+  static hipError_t rg_inv(const RgBase& base, const RgRowInv* tab, const RgItem* items,
+                           int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_inv_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
+                       base, tab, items);
+    return hipGetLastError();
+  }
 };
 
 #define GFC_ROW_ENTRY(n1, n2)                                                               \
   RowKernels{n1 * n2, n1, n2, RowCfg<n1, n2>::G, RowLaunch<n1, n2>::SLOTS,                   \
              &RowLaunch<n1, n2>::fwd, &RowLaunch<n1, n2>::inv, &RowLaunch<n1, n2>::bfwd,     \
-             &RowLaunch<n1, n2>::binv}
+             &RowLaunch<n1, n2>::binv, &RowLaunch<n1, n2>::rg_fwd, &RowLaunch<n1, n2>::rg_inv}
 
 }  // namespace gfc

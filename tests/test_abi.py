@@ -84,3 +84,30 @@ def test_supported_lengths_cover_the_workloads():
     for n in (64, 128, 512, 1024, 2048, 2400, 1620, 1200):
         assert gfc.supported_length(n), n
     assert not gfc.supported_length(22)
+
+
+def test_ragged_create_host_logic():
+    """Ragged objects are created on the host: sizes resolve to each image's default torus,
+    offsets are the packed prefix sums, bad sizes or flags are rejected."""
+    import gfc_synth as synth
+    sizes = [(64, 64), (37, 45), (801, 1200), (5, 3, 16, 16)]
+    r = gfc.Ragged(sizes)
+    assert r.B == 4
+    for (H, W, *mn), (h, w, M, N) in zip(sizes, r.sizes):
+        assert (h, w) == (H, W)
+        assert (M, N) == (tuple(mn) if mn else synth.default_grid(H, W))
+    assert list(r.offsets) == [0, 4096, 4096 + 37 * 45, 4096 + 37 * 45 + 801 * 1200,
+                               4096 + 37 * 45 + 801 * 1200 + 15]
+    L = gfc.lib()
+    h = ctypes.c_void_p()
+    H = (ctypes.c_int * 2)(10, 10)
+    W = (ctypes.c_int * 2)(10, 10)
+    N = (ctypes.c_int * 2)(0, 22)  # 22 has no row FFT
+    assert L.gfc_ragged_create(ctypes.byref(h), 2, H, W, None, N, 0) == 2
+    assert L.gfc_ragged_create(ctypes.byref(h), 2, H, W, None, None, 8) == 1
+    assert L.gfc_ragged_create(ctypes.byref(h), -1, H, W, None, None, 0) == 1
+    assert L.gfc_ragged_create(ctypes.byref(h), 2, H, W, None, None, 0) == 0
+    n = ctypes.c_size_t()
+    assert L.gfc_ragged_workspace_size(h, ctypes.byref(n)) == 3  # not built
+    assert L.gfc_ragged_solve(h, None, None, None, None, 0, None) == 3
+    L.gfc_ragged_destroy(h)
