@@ -43,39 +43,66 @@ __device__ __forceinline__ dc dsel(bool c, dc a, dc b) { return {c ? a.x : b.x, 
 // keeps the compiler from converting all register-held values to float64 at once
 __device__ __forceinline__ void pin(f2b& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 
+constexpr int kHorner = 8;  // LDS entries loaded together in the carry sums
+
+// acc <- sum_{t in [t0, t1)} r^(t1-1-t) A[t*C + c] (Horner from t0 upwards); the loads of a
+// chunk are issued together so the chain waits on LDS once per chunk, not per entry
+__device__ __forceinline__ dc horner_up(const dc* A, int C, int c, int t0, int t1, double r,
+                                        dc acc) {
+  int t = t0;
+  for (; t + kHorner <= t1; t += kHorner) {
+    dc e[kHorner];
+#pragma unroll
+    for (int q = 0; q < kHorner; ++q) e[q] = A[(t + q) * C + c];
+#pragma unroll
+    for (int q = 0; q < kHorner; ++q) acc = dfma(r, acc, e[q]);
+  }
+  for (; t < t1; ++t) acc = dfma(r, acc, A[t * C + c]);
+  return acc;
+}
+
+// acc <- sum_{t in (t0, t1]} r^(t-t0-1) A[t*C + c] + r^(t1-t0) acc (Horner from t1 down)
+__device__ __forceinline__ dc horner_down(const dc* A, int C, int c, int t1, int t0, double r,
+                                          dc acc) {
+  int t = t1;
+  for (; t - kHorner >= t0; t -= kHorner) {
+    dc e[kHorner];
+#pragma unroll
+    for (int q = 0; q < kHorner; ++q) e[q] = A[(t - q) * C + c];
+#pragma unroll
+    for (int q = 0; q < kHorner; ++q) acc = dfma(r, acc, e[q]);
+  }
+  for (; t > t0; --t) acc = dfma(r, acc, A[t * C + c]);
+  return acc;
+}
+
 // Carry into segment s from the segments before it: sum over t < s of
 // rho^(Lseg (s-1-t)) e_t (every segment before the last is Lseg rows), over at most kseg
 // segments. rp returns rho^(Lseg s) when the sum is exact (s <= kseg), else 0.
 __device__ __forceinline__ dc carry_in(const dc* E, int C, int c, int s, int kseg, double rhoL,
                                        double& rp) {
   const int t0 = s > kseg ? s - kseg : 0;
-  dc acc = {0.0, 0.0};
   double r = 1.0;
-  for (int t = t0; t < s; ++t) {
-    acc = dfma(rhoL, acc, E[t * C + c]);
-    r *= rhoL;
-  }
+  for (int t = 0; t < s && t <= kseg; ++t) r *= rhoL;
   rp = s > kseg ? 0.0 : r;
-  return acc;
+  return horner_up(E, C, c, t0, s, rhoL, dc{0.0, 0.0});
 }
 
 // z at the row after segment s (anticausal carry) from the moments zst_t of the later
 // segments and z[Rp] = ZR: Z_s = sum_{t > s} rho^(p_t - p_{s+1}) zst_t + rho^(Rp - p_{s+1}) ZR.
 __device__ __forceinline__ dc carry_out(const dc* U, int C, int c, int s, int last, int kseg,
                                         double rhoL, double rhoLl, dc ZR) {
-  const int tend = (s + kseg < last) ? s + kseg : last;
-  dc acc = (tend == last) ? ZR : dc{0.0, 0.0};
-  for (int t = tend; t > s; --t) acc = dfma(t == last ? rhoLl : rhoL, acc, U[t * C + c]);
-  return acc;
+  if (s == last) return ZR;
+  if (s + kseg < last) return horner_down(U, C, c, s + kseg, s, rhoL, dc{0.0, 0.0});
+  const dc acc = dfma(rhoLl, ZR, U[last * C + c]);  // z at the start of the last segment
+  return horner_down(U, C, c, last - 1, s, rhoL, acc);
 }
 
 // sum_t rho^(Lseg t) zst_t over the first kseg + 1 segments
 __device__ __forceinline__ dc head_moment(const dc* U, int C, int c, int last, int kseg,
                                           double rhoL) {
   const int tmax = kseg < last ? kseg : last;
-  dc acc = {0.0, 0.0};
-  for (int t = tmax; t >= 0; --t) acc = dfma(rhoL, acc, U[t * C + c]);
-  return acc;
+  return horner_down(U, C, c, tmax - 1, -1, rhoL, U[tmax * C + c]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -190,6 +217,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   if (col_ok) {
     if (dcol) {
       double pre = 0.0, tot = 0.0;
+#pragma unroll 8
       for (int t = 0; t < nseg; ++t) {
         const double x = E[t * C + c].x;
         pre += t < s ? x : 0.0;
@@ -394,6 +422,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
       // x-derivative symbol vanishes at l = 0).
       const int Rp = p.Rp;
       double pre = 0.0, tot = 0.0, sin_ = 0.0;
+#pragma unroll 8
       for (int t = 0; t < nseg; ++t) {
         const double x = E[t * C + c].x;
         pre += t < s ? x : 0.0;

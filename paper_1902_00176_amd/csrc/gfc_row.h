@@ -124,7 +124,7 @@ __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], floa
 // Rows of the block are processed in strips so the previous row's Ey^ stays in registers.
 // bx: block of SLOTS strips; b: image of the batch.
 template <int N1, int N2, int SLOTS>
-__device__ __forceinline__ void row_fwd_body(const RowFwdArgs& p, int bx, int b) {
+__device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
@@ -215,7 +215,7 @@ k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
 // Inverse row pass (row C2R of eq. (23), real part, crop and Algorithm B's constant).
 // Each slot handles p.ppw pairs of rows, two rows per complex inverse FFT.
 template <int N1, int N2, int SLOTS>
-__device__ __forceinline__ void row_inv_body(const RowInvArgs& p, int bx, int b) {
+__device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
