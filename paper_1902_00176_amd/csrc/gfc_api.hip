@@ -6,7 +6,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/gfc.h"
+#include "gfc.h"
 #include "gfc_internal.h"
 #include "gfc_plan.h"
 
@@ -176,6 +176,11 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
   p->Kb = std::min(kLowColsB, p->NH - 1);
   // row strides padded to whole 256-byte lines so column tiles never straddle cache lines
   p->NHP = (p->NH + 31) / 32 * 32;
+  // kernels address one image's buffers with 32-bit offsets below 2^30
+  if ((long long)(H + 1) * p->NHP * 8 >= (1LL << 30) || (long long)H * W * 4 >= (1LL << 30)) {
+    delete p;
+    return GFC_E_SIZE;
+  }
   p->KP = (p->K + 1 + 31) / 32 * 32;
   p->KbP = (p->Kb + 1 + 31) / 32 * 32;
   p->flags = flags;

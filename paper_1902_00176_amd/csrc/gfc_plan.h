@@ -6,7 +6,7 @@
 #include <algorithm>
 #include <cstddef>
 
-#include "../../include/gfc.h"
+#include "gfc.h"
 #include "gfc_internal.h"
 
 namespace gfc {

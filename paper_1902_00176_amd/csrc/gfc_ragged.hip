@@ -20,7 +20,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/gfc.h"
+#include "gfc.h"
 #include "gfc_internal.h"
 #include "gfc_plan.h"
 

@@ -297,7 +297,7 @@ k_row_bfwd(RowBwdFwdArgs p) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
-  __shared__ double s_sum[SLOTS * C::G];
+  __shared__ double s_sum[SLOTS];
   const int slot = threadIdx.x / C::G;
   const int lane = threadIdx.x % C::G;
   float* re = s_re[slot];
@@ -315,7 +315,6 @@ k_row_bfwd(RowBwdFwdArgs p) {
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
     cx a[N1];
-    float rs = 0.f;
     if (lane < N2) {
       const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
 #pragma unroll
@@ -325,11 +324,11 @@ k_row_bfwd(RowBwdFwdArgs p) {
         if (ok && x < p.W) e1 = bld1(rdu, v1, N2 * j1 * 4);
         if (has2 && x < p.W) e2 = bld1(rdu, v2, N2 * j1 * 4);
         a[j1] = {e1, e2};
-        rs += e1 + e2;
       }
     }
-    lsum += double(rs);
     fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
+    // the DC bin of the packed transform is (sum of row y1) + i (sum of row y2)
+    if (lane == 0) lsum += double(re[0]) + double(im[0]);
     if (ok) {
 #pragma unroll
       for (int i = 0; i < C::NI; ++i) {
@@ -345,11 +344,14 @@ k_row_bfwd(RowBwdFwdArgs p) {
     }
     slot_sync();
   }
-  s_sum[threadIdx.x] = lsum;
+  // per-workgroup sum: a fixed-order butterfly within each slot, then the slots in order
+#pragma unroll
+  for (int off = C::G / 2; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, C::G);
+  if (lane == 0) s_sum[slot] = lsum;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int i = 0; i < SLOTS * C::G; ++i) t += s_sum[i];
+    for (int i = 0; i < SLOTS; ++i) t += s_sum[i];
     p.sums[(long long)b * gridDim.x + blockIdx.x] = t;
   }
 }
