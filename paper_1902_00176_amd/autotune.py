@@ -5,7 +5,7 @@ the GPU (HIP events on the launch stream, median of several repetitions) over a 
 launch parameters, picks the fastest setting per parameter group and records it in
 tuning.json, which Plan() reads. Parameters only change speed, never results:
 
-  row_strip  rows per FFT slot in the strip-ordered row passes  (row forward, row backward-2)
+  row_strip  rows per FFT slot in the forward row pass
   row_ppw    row pairs per FFT slot in the pair-ordered passes  (row inverse, row backward-1)
   col_c      columns per workgroup in the column pass
   col_rows   most rows per thread in the column pass (16 | 32)
@@ -91,11 +91,11 @@ def tune_size(H, W, M, N, B, torch, verbose=True):
 
     best = dict(DEFAULT)
     log = []
-    # row strip: row forward + row backward-2
+    # row strip: row forward
     res = []
     for v in GRID["row_strip"]:
         t = run({**DEFAULT, "row_strip": v})
-        res.append((t["fwd1"] + t["bwd3"], v, t))
+        res.append((t["fwd1"], v, t))
         log.append({"row_strip": v, **t})
     best["row_strip"] = min(res)[1]
     # row pairs per slot: row inverse + row backward-1

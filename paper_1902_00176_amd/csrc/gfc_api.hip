@@ -123,7 +123,6 @@ void derive_geometry(gfc_plan_s* p) {
   p->gf = col_geometry(p->H + 1, p->M, p->r0, p->col_rows, p->col_c);
   p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows, p->col_c);
   p->nstrips_f = (p->H + 1 + p->row_strip - 1) / p->row_strip;
-  p->nstrips_b = (p->H + p->row_strip - 1) / p->row_strip;
   p->npairs = (p->H + 1) / 2;
   p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
   p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
@@ -416,8 +415,6 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     v.W = p->W;
     v.Kb = p->Kb;
     v.KbP = p->KbP;
-    v.strip = p->row_strip;
-    v.nstrips = p->nstrips_b;
     v.img_w = img_t;
     v.img_sd = img_sd;
     v.img_out = (long long)p->H * p->W;

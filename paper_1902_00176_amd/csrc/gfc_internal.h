@@ -64,7 +64,6 @@ struct RowBwdInvArgs {
   const f2* twB;
   const f2* sxm;      // [NH]: 1 - w_N^-l
   int H, W, Kb, KbP;
-  int strip, nstrips;
   long long img_w, img_sd, img_out;
 };
 

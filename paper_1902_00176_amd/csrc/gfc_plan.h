@@ -34,7 +34,7 @@ struct gfc_plan_s {
   // launch geometry (gfc_plan_set_param) and what follows from it
   int row_strip = gfc::kRowStrip, row_ppw = gfc::kPairsPerSlot, col_c = gfc::kColC,
       col_rows = gfc::kColRows;
-  int nstrips_f = 0, nstrips_b = 0, npairs = 0;
+  int nstrips_f = 0, npairs = 0;
   int ntiles_f = 0, ntiles_b = 0, nsums = 0;
   // device tables, one allocation (gfc_green_build)
   bool built = false;

@@ -370,9 +370,10 @@ k_row_binv(RowBwdInvArgs p) {
   float* re = s_re[slot];
   float* im = s_im[slot];
   const int b = blockIdx.y;
-  const int strip = blockIdx.x * SLOTS + slot;
-  const bool strip_ok = strip < p.nstrips;
-  const int y0 = strip * p.strip;
+  // one row per slot: carrying row y + 1 into the next row's iteration costs more
+  // registers than reading it again from cache
+  const int y = blockIdx.x * SLOTS + slot;
+  const bool row_ok = y < p.H;
   const int Kb1 = p.KbP;
   const rsrc_t rW = make_buf(p.Wv + b * p.img_w, p.img_w * 8);
   const rsrc_t rSD = make_buf(p.SD + b * p.img_sd, p.img_sd * 8);
@@ -380,73 +381,59 @@ k_row_binv(RowBwdInvArgs p) {
   const rsrc_t rgy = make_buf(p.dgy + b * p.img_out, p.img_out * 4);
   const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
   const rsrc_t rsxm = make_buf(p.sxm, (long long)C::NH * 8);
+  const int tz = fresh_zero();
 
-  cx cur[C::NI];
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) {
     const int l = lane + C::G * i;
-    cur[i] = {0.f, 0.f};
-    if (strip_ok && l < C::NH && y0 < p.H) {
-      const f2b v = bld2(rW, (y0 * C::NHP + lane) * 8, C::G * i * 8);
-      cur[i] = {v.x, v.y};
+    if (l < C::NH) {
+      cx cur = {0.f, 0.f}, nxt = {0.f, 0.f};
+      if (row_ok) {
+        const f2b v0 = bld2(rW, (y * C::NHP + lane) * 8, C::G * i * 8);
+        const f2b v1 = bld2(rW, ((y + 1) * C::NHP + lane) * 8, C::G * i * 8);
+        cur = {v0.x, v0.y};
+        nxt = {v1.x, v1.y};
+      }
+      const f2b sm = bld2(rsxm, lane * 8, tz + C::G * i * 8);
+      const cx X1 = cmul(cx{sm.x, sm.y}, cur);
+      cx X2;
+      if (l <= p.Kb) {
+        X2 = {0.f, 0.f};
+        if (row_ok) {
+          const f2b v = bld2(rSD, (y * Kb1 + lane) * 8, C::G * i * 8);
+          X2 = {v.x, v.y};
+        }
+      } else {
+        X2 = csub(cur, nxt);
+      }
+      // full spectrum of dgx + i dgy at bins l and N - l
+      re[l] = X1.x - X2.y;
+      im[l] = X1.y + X2.x;
+      if (l != 0 && 2 * l != C::N) {
+        re[C::N - l] = X1.x + X2.y;
+        im[C::N - l] = X2.x - X1.y;
+      }
     }
   }
-  for (int it = 0; it < p.strip; ++it) {
-    const int tz = fresh_zero();
-    const int y = y0 + it;
-    const bool row_ok = strip_ok && y < p.H;
+  slot_sync();
+  cx bz[N2];
+  if (lane < N1) {
 #pragma unroll
-    for (int i = 0; i < C::NI; ++i) {
-      const int l = lane + C::G * i;
-      if (l < C::NH) {
-        cx nxt = {0.f, 0.f};
-        if (row_ok) {
-          const f2b v = bld2(rW, ((y + 1) * C::NHP + lane) * 8, C::G * i * 8);
-          nxt = {v.x, v.y};
-        }
-        const f2b sm = bld2(rsxm, lane * 8, tz + C::G * i * 8);
-        const cx X1 = cmul(cx{sm.x, sm.y}, cur[i]);
-        cx X2;
-        if (l <= p.Kb) {
-          X2 = {0.f, 0.f};
-          if (row_ok) {
-            const f2b v = bld2(rSD, (y * Kb1 + lane) * 8, C::G * i * 8);
-            X2 = {v.x, v.y};
-          }
-        } else {
-          X2 = csub(cur[i], nxt);
-        }
-        // full spectrum of dgx + i dgy at bins l and N - l
-        re[l] = X1.x - X2.y;
-        im[l] = X1.y + X2.x;
-        if (l != 0 && 2 * l != C::N) {
-          re[C::N - l] = X1.x + X2.y;
-          im[C::N - l] = X2.x - X1.y;
-        }
-        cur[i] = nxt;
+    for (int k2 = 0; k2 < N2; ++k2) bz[k2] = {re[lane + N1 * k2], im[lane + N1 * k2]};
+  }
+  slot_sync();
+  cx a[N1];
+  inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
+  if (lane < N2 && row_ok) {
+    const int vo = (y * p.W + lane) * 4;
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) {
+      const int x = lane + N2 * j1;
+      if (x < p.W) {
+        bst1(rgx, a[j1].x, vo, N2 * j1 * 4);
+        bst1(rgy, a[j1].y, vo, N2 * j1 * 4);
       }
     }
-    slot_sync();
-    cx bz[N2];
-    if (lane < N1) {
-#pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) bz[k2] = {re[lane + N1 * k2], im[lane + N1 * k2]};
-    }
-    slot_sync();
-    cx a[N1];
-    inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
-    if (lane < N2 && row_ok) {
-      const int vo = (y * p.W + lane) * 4;
-#pragma unroll
-      for (int j1 = 0; j1 < N1; ++j1) {
-        const int x = lane + N2 * j1;
-        if (x < p.W) {
-          bst1(rgx, a[j1].x, vo, N2 * j1 * 4);
-          bst1(rgy, a[j1].y, vo, N2 * j1 * 4);
-        }
-      }
-    }
-    slot_sync();
   }
 }
 
@@ -475,7 +462,7 @@ struct RowLaunch {
     return hipGetLastError();
   }
   static hipError_t binv(const RowBwdInvArgs& a, int B, hipStream_t s) {
-    dim3 grid((a.nstrips + SLOTS - 1) / SLOTS, B);
+    dim3 grid((a.H + SLOTS - 1) / SLOTS, B);  // one row per slot
     hipLaunchKernelGGL((k_row_binv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
