@@ -28,9 +28,9 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import paper_1902_00176_amd as gfc  # noqa: E402
 
-DEFAULT = {"row_strip": 16, "row_ppw": 1, "col_c": 16, "col_rows": 32}
+DEFAULT = {"row_strip": 8, "row_ppw": 1, "col_c": 16, "col_rows": 16}
 GRID = {
-    "row_strip": [4, 8, 16, 32],
+    "row_strip": [4, 6, 8, 12, 16],
     "row_ppw": [1, 2, 4],
     "col": [(c, r) for c in (4, 8, 16, 32) for r in (16, 32)],
 }

@@ -156,7 +156,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
       const int vo = (y * p.W + lane) * 4;
 #pragma unroll
       for (int y1 = 0; y1 < N1; ++y1) {
-        const int x = N2 * y1 + lane;
+        // tz keeps the bounds tests inside the row loop (hoisted, their masks spill)
+        const int x = N2 * y1 + lane + tz;
         if (row_in && x < p.W) {
           a[y1] = {bld1(rgx, vo, N2 * y1 * 4), bld1(rgy, vo, N2 * y1 * 4)};
         } else {
@@ -260,7 +261,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) 
       const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
-        const int x = lane + N2 * j1;
+        const int x = lane + N2 * j1 + tz;  // tz: bounds tests stay inside the loop
         if (x < p.W) {
           bst1(ru, a[j1].x - vref, v1, N2 * j1 * 4);
           if (has2) bst1(ru, a[j1].y - vref, v2, N2 * j1 * 4);
@@ -319,7 +320,7 @@ k_row_bfwd(RowBwdFwdArgs p) {
       const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
-        const int x = N2 * j1 + lane;
+        const int x = N2 * j1 + lane + tz;  // tz: bounds tests stay inside the loop
         float e1 = 0.f, e2 = 0.f;
         if (ok && x < p.W) e1 = bld1(rdu, v1, N2 * j1 * 4);
         if (has2 && x < p.W) e2 = bld1(rdu, v2, N2 * j1 * 4);
@@ -443,7 +444,8 @@ k_row_binv(RowBwdInvArgs p) {
 template <int N1, int N2>
 struct RowLaunch {
   using C = RowCfg<N1, N2>;
-  static constexpr int SLOTS = 256 / C::G;
+  // 64-lane slots run one wavefront per workgroup; narrower slots fill 256-thread groups
+  static constexpr int SLOTS = C::G == 64 ? 1 : 256 / C::G;
   static hipError_t fwd(const RowFwdArgs& a, int B, hipStream_t s) {
     dim3 grid((a.nstrips + SLOTS - 1) / SLOTS, B);
     hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
