@@ -22,8 +22,11 @@
  *    aligned, owned by the caller. Its contents need not be initialised and are undefined
  *    after a call. Two calls that run concurrently need separate workspaces.
  *  - `stream` is a hipStream_t (NULL = the default stream). Solve calls only enqueue
- *    kernels on it: they never allocate, never synchronise and never copy host data.
- *    Asynchronous kernel errors surface as GFC_E_HIP on a later call.
+ *    work: they never allocate, never synchronise the host and never copy host data. The
+ *    forward column pass runs its few lowest-column tiles on a side stream owned by the
+ *    plan, forked from and joined back to `stream` with events, so `stream` sees the
+ *    call complete in order (graph capture follows the fork). Asynchronous kernel errors
+ *    surface as GFC_E_HIP on a later call.
  *  - A plan owns its device tables (created by gfc_green_build) and is immutable after
  *    that call, so it may be used from several streams with separate workspaces.
  *  - Errors are returned as status codes; nothing is ever thrown across this ABI.

@@ -294,6 +294,10 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   p->ccf = reinterpret_cast<ColConst*>(base + o_ccf);
   p->ccb = reinterpret_cast<ColConst*>(base + o_ccb);
   (void)hipGetDevice(&p->device);
+  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
+    return GFC_E_HIP;
   p->built = true;
   return GFC_OK;
 }
@@ -326,7 +330,8 @@ gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 2) {
-    const gfc_status st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s));
+    const gfc_status st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s,
+                                                    p->side, p->ev_fork, p->ev_join));
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 3) {
@@ -452,6 +457,9 @@ void gfc_plan_destroy(gfc_plan_t p) {
     (void)hipGetDevice(&cur);
     if (p->device >= 0 && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipFree(p->dmem);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->side) (void)hipStreamDestroy(p->side);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
   }
   delete p;

@@ -509,12 +509,12 @@ int col_block(int C, int nseg) { return (C * nseg + 63) / 64 * 64; }
 
 template <int LMAX, bool TAIL>
 void launch_fwd_tiles(const ColFwdArgs& a, int ntiles, int nlow, int B, size_t shm,
-                      hipStream_t s) {
+                      hipStream_t s, hipStream_t s_low) {
   const dim3 blk(col_block(a.C, a.nseg));
   ColFwdArgs x = a;
   if (nlow > 0) {
     x.tile0 = 0;
-    hipLaunchKernelGGL((k_col_fwd<LMAX, true, TAIL>), dim3(nlow, B), blk, shm, s, x);
+    hipLaunchKernelGGL((k_col_fwd<LMAX, true, TAIL>), dim3(nlow, B), blk, shm, s_low, x);
   }
   if (ntiles > nlow) {
     x.tile0 = nlow;
@@ -524,22 +524,38 @@ void launch_fwd_tiles(const ColFwdArgs& a, int ntiles, int nlow, int B, size_t s
 }  // namespace
 
 // Tiles that hold columns l <= K are launched separately so the split-input path costs
-// no registers in the others.
-hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s) {
+// no registers in the others. Given a side stream and two events, the few low tiles run
+// there, beside the other tiles, and `s` waits for them: they are a small, latency-bound
+// launch that would otherwise run alone.
+hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t side,
+                          hipEvent_t fork, hipEvent_t join) {
   const size_t shm = size_t(2 * a.nseg * a.C) * sizeof(dc);
   const int ntiles = (a.NH + a.C - 1) / a.C;
   const int nlow = std::min(ntiles, (a.K + 1 + a.C - 1) / a.C);
   const bool tail = a.Rp != a.nseg * a.Lseg;
+  const bool split = side && fork && join && nlow > 0 && ntiles > nlow;
+  hipStream_t s_low = s;
+  if (split) {
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+    s_low = side;
+  }
   if (a.Lseg == 16) {
-    if (tail) launch_fwd_tiles<16, true>(a, ntiles, nlow, B, shm, s);
-    else launch_fwd_tiles<16, false>(a, ntiles, nlow, B, shm, s);
+    if (tail) launch_fwd_tiles<16, true>(a, ntiles, nlow, B, shm, s, s_low);
+    else launch_fwd_tiles<16, false>(a, ntiles, nlow, B, shm, s, s_low);
   } else if (a.Lseg == 32) {
-    if (tail) launch_fwd_tiles<32, true>(a, ntiles, nlow, B, shm, s);
-    else launch_fwd_tiles<32, false>(a, ntiles, nlow, B, shm, s);
+    if (tail) launch_fwd_tiles<32, true>(a, ntiles, nlow, B, shm, s, s_low);
+    else launch_fwd_tiles<32, false>(a, ntiles, nlow, B, shm, s, s_low);
   } else {
     return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (split && e == hipSuccess) {
+    e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+  }
+  return e;
 }
 
 namespace {

@@ -167,7 +167,8 @@ const RowKernels* find_row_kernels(int N);
 int row_kernel_count();
 const RowKernels* row_kernel_at(int i);
 
-hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s);
+hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t side = nullptr,
+                          hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
 // ragged forward column pass: items of tiles holding columns l <= K and of the others,
 // one workgroup shape (threads, LDS bytes) for all images, rows per segment Lseg

@@ -42,6 +42,9 @@ struct gfc_plan_s {
   void* dmem = nullptr;
   gfc::f2 *twA = nullptr, *twB = nullptr, *sx = nullptr, *sxm = nullptr, *dshift = nullptr;
   gfc::ColConst *ccf = nullptr, *ccb = nullptr;
+  // a side stream for the forward column pass's low tiles, joined back with two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace gfc {

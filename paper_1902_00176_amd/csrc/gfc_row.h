@@ -46,6 +46,20 @@ __device__ __forceinline__ void slot_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2. This maps
+// the linear workgroup index so that every XCD receives a contiguous range of blocks:
+// neighbouring rows, which share their boundary row, then meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_contiguous(int& bx, int& by) {
+  const int total = gridDim.x * gridDim.y;
+  const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+  const int q = total / kXcds, r = total % kXcds;
+  const int xcd = lin % kXcds, pos = lin / kXcds;
+  const int nl = xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+  bx = nl % gridDim.x;
+  by = nl / gridDim.x;
+}
+
 // An integer the optimiser must treat as changed at each loop iteration: added to the uniform
 // offsets of loop-invariant table loads so they are issued where used instead of being
 // hoisted out of the row loop and held live. Empty asm: no instruction is emitted.
@@ -195,7 +209,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
 template <int N1, int N2, int SLOTS>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_fwd(RowFwdArgs p) {
-  row_fwd_body<N1, N2, SLOTS>(p, blockIdx.x, blockIdx.y);
+  int bx, by;
+  xcd_contiguous(bx, by);
+  row_fwd_body<N1, N2, SLOTS>(p, bx, by);
 }
 
 // ragged batches: one work item (image, block) per workgroup; pointers rebased per image
@@ -370,10 +386,12 @@ k_row_binv(RowBwdInvArgs p) {
   const int lane = threadIdx.x % C::G;
   float* re = s_re[slot];
   float* im = s_im[slot];
-  const int b = blockIdx.y;
+  int bx, b;
+  xcd_contiguous(bx, b);
   // one row per slot: carrying row y + 1 into the next row's iteration costs more
-  // registers than reading it again from cache
-  const int y = blockIdx.x * SLOTS + slot;
+  // registers than reading it again from cache (the neighbour row's workgroup runs on
+  // the same XCD)
+  const int y = bx * SLOTS + slot;
   const bool row_ok = y < p.H;
   const int Kb1 = p.KbP;
   const rsrc_t rW = make_buf(p.Wv + b * p.img_w, p.img_w * 8);
