@@ -183,8 +183,8 @@ def main():
         pmc_summarize(*args.pmc_summarize, os.path.join(ROOT, "profiles", "traffic.json"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the solve on a single MI355X "
-              "(the batch shards by image across GPUs with no exchange; see DESIGN.md).",
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(a batch shards by image across GPUs with no exchange).",
               file=sys.stderr)
         sys.exit(2)
 

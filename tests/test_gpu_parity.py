@@ -29,7 +29,7 @@ def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     if not os.path.exists(gfc.lib_path()):
-        pytest.fail("libgfc.so is not built: the HIP path must exist on a GPU box")
+        pytest.fail("libgfc.so is not built: the HIP path must exist where a GPU is present")
 
 
 def rel_l2(a, b):
