@@ -5,7 +5,7 @@ the GPU (HIP events on the launch stream, median of several repetitions) over a 
 launch parameters, picks the fastest setting per parameter group and records it in
 tuning.json, which Plan() reads. Parameters only change speed, never results:
 
-  row_strip  rows per FFT slot in the forward row pass
+  row_fppw   pairs of divergence rows per FFT slot in the forward row pass
   row_ppw    row pairs per FFT slot in the pair-ordered passes  (row inverse, row backward-1)
   col_c      columns per workgroup in the column pass
   col_rows   most rows per thread in the column pass (16 | 32)
@@ -28,9 +28,9 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import paper_1902_00176_amd as gfc  # noqa: E402
 
-DEFAULT = {"row_strip": 8, "row_ppw": 1, "col_c": 16, "col_rows": 16}
+DEFAULT = {"row_fppw": 1, "row_ppw": 1, "col_c": 16, "col_rows": 16}
 GRID = {
-    "row_strip": [4, 6, 8, 12, 16],
+    "row_fppw": [1, 2, 4],
     "row_ppw": [1, 2, 4],
     "col": [(c, r) for c in (4, 8, 16, 32) for r in (16, 32)],
 }
@@ -91,13 +91,13 @@ def tune_size(H, W, M, N, B, torch, verbose=True):
 
     best = dict(DEFAULT)
     log = []
-    # row strip: row forward
+    # pairs per slot: row forward
     res = []
-    for v in GRID["row_strip"]:
-        t = run({**DEFAULT, "row_strip": v})
+    for v in GRID["row_fppw"]:
+        t = run({**DEFAULT, "row_fppw": v})
         res.append((t["fwd1"], v, t))
-        log.append({"row_strip": v, **t})
-    best["row_strip"] = min(res)[1]
+        log.append({"row_fppw": v, **t})
+    best["row_fppw"] = min(res)[1]
     # row pairs per slot: row inverse + row backward-1
     res = []
     for v in GRID["row_ppw"]:

@@ -122,7 +122,7 @@ void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
 void derive_geometry(gfc_plan_s* p) {
   p->gf = col_geometry(p->H + 1, p->M, p->r0, p->col_rows, p->col_c);
   p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows, p->col_c);
-  p->nstrips_f = (p->H + 1 + p->row_strip - 1) / p->row_strip;
+  p->nfslots = ((p->H + 2) / 2 + p->row_fppw - 1) / p->row_fppw;
   p->npairs = (p->H + 1) / 2;
   p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
   p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
@@ -171,8 +171,8 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
   p->ox = (N - W) / 2;
   p->r0 = M - p->oy;  // grid corner (0,0) relative to the block at the origin
   p->c0 = N - p->ox;
-  p->K = std::min(kLowCols, p->NH - 1);
-  p->Kb = std::min(kLowColsB, p->NH - 1);
+  p->K = kLowBins;  // the row lengths compiled in all have N / 2 > kLowBins
+  p->Kb = std::min(kLowBinsB, p->NH - 1);
   // row strides padded to whole 256-byte lines so column tiles never straddle cache lines
   p->NHP = (p->NH + 31) / 32 * 32;
   // kernels address one image's buffers with 32-bit offsets below 2^30
@@ -180,7 +180,7 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
     delete p;
     return GFC_E_SIZE;
   }
-  p->KP = (p->K + 1 + 31) / 32 * 32;
+  p->KP = (p->K + 1 + 7) / 8 * 8;
   p->KbP = (p->Kb + 1 + 31) / 32 * 32;
   p->flags = flags;
   p->rk = rk;
@@ -203,9 +203,9 @@ gfc_status gfc_plan_get(gfc_plan_t p, int* H, int* W, int* M, int* N, int* oy, i
 gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
   if (!p || !name) return GFC_E_ARG;
   if (p->built) return GFC_E_ARG;  // the float64 tables depend on the geometry
-  if (!std::strcmp(name, "row_strip")) {
-    if (value < 1 || value > 256) return GFC_E_ARG;
-    p->row_strip = value;
+  if (!std::strcmp(name, "row_fppw")) {
+    if (value < 1 || value > 64) return GFC_E_ARG;
+    p->row_fppw = value;
   } else if (!std::strcmp(name, "row_ppw")) {
     if (value < 1 || value > 64) return GFC_E_ARG;
     p->row_ppw = value;
@@ -224,7 +224,7 @@ gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
 
 gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
   if (!p || !name || !value) return GFC_E_ARG;
-  if (!std::strcmp(name, "row_strip")) *value = p->row_strip;
+  if (!std::strcmp(name, "row_fppw")) *value = p->row_fppw;
   else if (!std::strcmp(name, "row_ppw")) *value = p->row_ppw;
   else if (!std::strcmp(name, "col_c")) *value = p->gf.C;
   else if (!std::strcmp(name, "col_rows")) *value = p->col_rows;
@@ -237,7 +237,24 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   if (p->built) return GFC_OK;
   const int N = p->N, N1 = p->rk->N1, N2 = p->rk->N2, NH = p->NH;
   // four-step twiddles w_N^(k1 j): [N1][N2] for the forward step, [N2][N1] for the inverse
-  std::vector<f2> twA(size_t(N1) * N2), twB(size_t(N1) * N2), sx(NH), sxm(NH), dsh(NH);
+  std::vector<f2> twA(size_t(N1) * N2), twB(size_t(N1) * N2), sxm(NH), dsh(NH);
+  // low-bin twiddles of the forward row pass, lane j < N2 of a G-lane slot:
+  // [0][l][j] = (1 - w_N^l) w_N^(l j) for Ex, [1][l][j] = w_N^(l j) for Ey (0 for j >= N2)
+  const int G = p->rk->G, K1 = p->K + 1;
+  std::vector<f2> twL(size_t(2) * K1 * G, f2{0.f, 0.f});
+  for (int l = 0; l < K1; ++l) {
+    const double h = std::sin(kPi * double(l) / double(N));
+    double c, s;
+    cs2pi(l, N, c, s);
+    const double ar = 2.0 * h * h, ai = s;  // 1 - e^{-i 2 pi l / N}
+    for (int j = 0; j < N2; ++j) {
+      double cj, sj;
+      cs2pi(long(l) * j, N, cj, sj);
+      const double wr = cj, wi = -sj;  // e^{-i 2 pi l j / N}
+      twL[size_t(l) * G + j] = f2{float(ar * wr - ai * wi), float(ar * wi + ai * wr)};
+      twL[size_t(K1 + l) * G + j] = f2{float(wr), float(wi)};
+    }
+  }
   for (int k1 = 0; k1 < N1; ++k1)
     for (int j = 0; j < N2; ++j) {
       double c, s;
@@ -250,7 +267,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
     cs2pi(l, N, c, s);
     const double h = std::sin(kPi * double(l) / double(N));
     const double omc = 2.0 * h * h;  // 1 - cos(2 pi l / N)
-    sx[l] = f2{float(omc), float(s)};    // 1 - e^{-i theta}
     sxm[l] = f2{float(omc), float(-s)};  // 1 - e^{+i theta}
     cs2pi(long(l) * p->c0, N, c, s);
     dsh[l] = f2{float(c), float(-s)};    // e^{-2 pi i l c0 / N}
@@ -262,7 +278,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   size_t off = 0;
   const size_t o_twA = off; off = align256(off + twA.size() * sizeof(f2));
   const size_t o_twB = off; off = align256(off + twB.size() * sizeof(f2));
-  const size_t o_sx = off; off = align256(off + sx.size() * sizeof(f2));
+  const size_t o_twL = off; off = align256(off + twL.size() * sizeof(f2));
   const size_t o_sxm = off; off = align256(off + sxm.size() * sizeof(f2));
   const size_t o_dsh = off; off = align256(off + dsh.size() * sizeof(f2));
   const size_t o_ccf = off; off = align256(off + ccf.size() * sizeof(ColConst));
@@ -270,7 +286,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   std::vector<unsigned char> host(off, 0);
   std::memcpy(host.data() + o_twA, twA.data(), twA.size() * sizeof(f2));
   std::memcpy(host.data() + o_twB, twB.data(), twB.size() * sizeof(f2));
-  std::memcpy(host.data() + o_sx, sx.data(), sx.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twL, twL.data(), twL.size() * sizeof(f2));
   std::memcpy(host.data() + o_sxm, sxm.data(), sxm.size() * sizeof(f2));
   std::memcpy(host.data() + o_dsh, dsh.data(), dsh.size() * sizeof(f2));
   std::memcpy(host.data() + o_ccf, ccf.data(), ccf.size() * sizeof(ColConst));
@@ -288,7 +304,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   p->dmem = d;
   p->twA = reinterpret_cast<f2*>(base + o_twA);
   p->twB = reinterpret_cast<f2*>(base + o_twB);
-  p->sx = reinterpret_cast<f2*>(base + o_sx);
+  p->twL = reinterpret_cast<f2*>(base + o_twL);
   p->sxm = reinterpret_cast<f2*>(base + o_sxm);
   p->dshift = reinterpret_cast<f2*>(base + o_dsh);
   p->ccf = reinterpret_cast<ColConst*>(base + o_ccf);

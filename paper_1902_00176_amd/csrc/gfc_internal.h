@@ -11,18 +11,20 @@ struct f2 {
 
 // ---- row passes -----------------------------------------------------------------------
 // Forward row pass: for each row y in [0, H] of the divergence L (block at the torus
-// origin), T1[y, l] = (1 - w_N^l) Ex^[y, l] + Ey^[y, l] - Ey^[y-1, l] for l > K, and the
-// split form T1[y, l] = (1 - w_N^l) Ex^[y, l], SB[y, l] = Ey^[y, l] for l <= K.
+// origin), T1[y, l] = L^[y, l] for l > K, and the split form T1[y, l] = (1 - w_N^l) Ex^[y, l],
+// SB[y, l] = Ey^[y, l] for l <= K (T1[y, 0] = 0). L is formed in float32 from the gradient
+// and two rows of L share one complex FFT; the K + 1 lowest bins of Ex and Ey are direct sums.
+constexpr int kLowBins = 4;  // K: row frequencies l <= K arrive at the column pass split
 struct RowFwdArgs {
   const float* gx;
   const float* gy;
   f2* T1;             // [B][H+1][NHP]  (NHP = NH rounded up to 32: row stride)
   f2* SB;             // [B][H][KP]     (KP = side-array row stride >= K + 1)
   const f2* twA;      // [N1][N2]: w_N^(k1 j), forward sign
-  const f2* sx;       // [NH]: 1 - w_N^l
+  const f2* twL;      // [2][K+1][G]: (1 - w_N^l) w_N^(l j) and w_N^(l j), 0 for j >= N2
   int H, W, K, KP;
-  int strip;          // rows per slot
-  int nstrips;        // ceil((H+1) / strip)
+  int ppw;            // pairs of L rows per slot
+  int npairs;         // ceil((H+1) / 2)
   long long img_in, img_t1, img_sb;
 };
 
@@ -52,6 +54,8 @@ struct RowBwdFwdArgs {
   int ppw;
   long long img_in, img_u;
 };
+
+constexpr int kLowBinsB = 64;  // Kb: backward columns l <= Kb take -D_y inside the recursion
 
 // Backward row pass 2: per row y in [0, H): Zx = (1 - w_N^-l) Wv[y, l],
 // Zy = SD[y, l] (l <= Kb) or Wv[y, l] - Wv[y+1, l] (l > Kb); one complex inverse FFT of
@@ -160,7 +164,8 @@ struct RowKernels {
   hipError_t (*inv)(const RowInvArgs&, int B, hipStream_t);
   hipError_t (*bfwd)(const RowBwdFwdArgs&, int B, hipStream_t);
   hipError_t (*binv)(const RowBwdInvArgs&, int B, hipStream_t);
-  hipError_t (*rg_fwd)(const RgBase&, const RgRowFwd*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*rg_fwd)(const RgBase&, const RgRowFwd*, const RgItem*, int nitems, bool half,
+                       hipStream_t);
   hipError_t (*rg_inv)(const RgBase&, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
 };
 const RowKernels* find_row_kernels(int N);

@@ -11,10 +11,8 @@
 
 namespace gfc {
 
-constexpr int kLowCols = 16;    // forward: columns l <= K use the split (x-spectral) input
-constexpr int kLowColsB = 64;   // backward: columns l <= Kb take -D_y inside the recursion
 // Launch geometry defaults; each can be changed per plan with gfc_plan_set_param.
-constexpr int kRowStrip = 4;      // "row_strip": rows per slot in the strip-ordered row passes
+constexpr int kFwdPairsPerSlot = 1;  // "row_fppw": pairs of L rows per slot, forward row pass
 constexpr int kColC = 16;         // "col_c": columns per workgroup in the column pass
 constexpr int kColRows = 16;      // "col_rows": rows per thread in the column pass (16|32)
 constexpr int kPairsPerSlot = 1;  // "row_ppw": row pairs per slot in the pair-ordered passes
@@ -32,15 +30,15 @@ struct gfc_plan_s {
   const gfc::RowKernels* rk = nullptr;
   gfc::ColGeom gf{}, gb{};
   // launch geometry (gfc_plan_set_param) and what follows from it
-  int row_strip = gfc::kRowStrip, row_ppw = gfc::kPairsPerSlot, col_c = gfc::kColC,
+  int row_fppw = gfc::kFwdPairsPerSlot, row_ppw = gfc::kPairsPerSlot, col_c = gfc::kColC,
       col_rows = gfc::kColRows;
-  int nstrips_f = 0, npairs = 0;
+  int nfslots = 0, npairs = 0;
   int ntiles_f = 0, ntiles_b = 0, nsums = 0;
   // device tables, one allocation (gfc_green_build)
   bool built = false;
   int device = -1;
   void* dmem = nullptr;
-  gfc::f2 *twA = nullptr, *twB = nullptr, *sx = nullptr, *sxm = nullptr, *dshift = nullptr;
+  gfc::f2 *twA = nullptr, *twB = nullptr, *twL = nullptr, *sxm = nullptr, *dshift = nullptr;
   gfc::ColConst *ccf = nullptr, *ccb = nullptr;
   // a side stream for the forward column pass's low tiles, joined back with two events
   hipStream_t side = nullptr;
@@ -76,13 +74,13 @@ inline RowFwdArgs row_fwd_args(const gfc_plan_s* p, const float* gx, const float
   a.T1 = T;
   a.SB = SB;
   a.twA = p->twA;
-  a.sx = p->sx;
+  a.twL = p->twL;
   a.H = p->H;
   a.W = p->W;
   a.K = p->K;
   a.KP = p->KP;
-  a.strip = p->row_strip;
-  a.nstrips = p->nstrips_f;
+  a.ppw = p->row_fppw;
+  a.npairs = (p->H + 2) / 2;
   a.img_in = (long long)p->H * p->W;
   a.img_t1 = (long long)(p->H + 1) * p->NHP;
   a.img_sb = (long long)p->H * p->KP;

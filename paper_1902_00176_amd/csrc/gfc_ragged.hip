@@ -60,6 +60,7 @@ struct gfc_ragged_s {
   struct Group {
     const RowKernels* rk;
     int f_off, f_n, i_off, i_n;
+    bool half;  // every image of the group has 2 W <= N
   };
   std::vector<Group> groups;  // one per distinct N
   int c_low_off = 0, c_low_n = 0, c_rest_off = 0, c_rest_n = 0;
@@ -109,7 +110,7 @@ gfc_status enqueue(gfc_ragged_s* r, const RgBase& base, hipStream_t main) {
   for (size_t g = 0; g < r->groups.size(); ++g) {
     const auto& G = r->groups[g];
     if (G.f_n > 0 &&
-        G.rk->rg_fwd(base, r->tab_f, r->items + G.f_off, G.f_n, st[g % kRgStreams]) != hipSuccess)
+        G.rk->rg_fwd(base, r->tab_f, r->items + G.f_off, G.f_n, G.half, st[g % kRgStreams]) != hipSuccess)
       return GFC_E_HIP;
   }
   if (!join(kRgStreams)) return GFC_E_HIP;
@@ -248,10 +249,12 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
     g.rk = r->plans[r->plan_of[first]]->rk;
     const int slots = g.rk->slots;
     g.f_off = int(items.size());
+    g.half = true;
     for (int i : order) {
       if (r->N[i] != n) continue;
+      g.half = g.half && 2 * r->W[i] <= n;
       const gfc_plan_s* p = r->plans[r->plan_of[i]];
-      const int nb = (p->nstrips_f + slots - 1) / slots;
+      const int nb = (p->nfslots + slots - 1) / slots;
       for (int k = 0; k < nb; ++k) items.push_back(RgItem{i, k});
     }
     g.f_n = int(items.size()) - g.f_off;

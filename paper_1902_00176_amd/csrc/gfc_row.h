@@ -14,6 +14,8 @@
 #include "gfc_dft.h"
 #include "gfc_internal.h"
 
+#include <utility>
+
 namespace gfc {
 
 constexpr int pow2ceil(int v) { return v <= 8 ? 8 : v <= 16 ? 16 : v <= 32 ? 32 : 64; }
@@ -135,87 +137,244 @@ __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], floa
 
 // ---------------------------------------------------------------------------------------
 // Forward row pass (divergence + row R2C, eq. (3) and the row half of F(L) in eq. (23)).
-// Rows of the block are processed in strips so the previous row's Ey^ stays in registers.
-// bx: block of SLOTS strips; b: image of the batch.
-template <int N1, int N2, int SLOTS>
+//
+// Each slot takes pairs of rows (y, y + 1) of L = div E, formed in float32 from the loaded
+// gradient, and transforms them as one complex FFT of L[y] + i L[y + 1]. The bins l <= K go
+// to the column pass in the split form (1 - w_N^l) Ex^ and Ey^ instead: those are direct
+// sums over the undifferenced rows, because an FFT of L leaves a rounding error of the
+// size of |L| in every bin, and the column Green's function amplifies the lowest bins by
+// up to 1/lambda(0, 1). In lane j, x = N2 y1 + j and w_N^(l x) = w_N1^(l y1) w_N^(l j): the
+// y1 sums take compile-time constants, the lane factor comes from a float64-built table, and
+// an LDS transpose sums the lanes.
+
+// acc += v * w_N^E (forward sign) for real v; trivial constants cost one add or nothing
+template <int N, int E>
+__device__ __forceinline__ void acc_tw(cx& acc, float v) {
+  constexpr int e = ((E % N) + N) % N;
+  if constexpr (e == 0) {
+    acc.x += v;
+  } else if constexpr (2 * e == N) {
+    acc.x -= v;
+  } else if constexpr (4 * e == N) {
+    acc.y -= v;
+  } else if constexpr (4 * e == 3 * N) {
+    acc.y += v;
+  } else {
+    constexpr float c = float(detail::cs2pi(e, N, 0));
+    constexpr float sn = float(-detail::cs2pi(e, N, 1));
+    acc.x = __builtin_fmaf(v, c, acc.x);
+    acc.y = __builtin_fmaf(v, sn, acc.y);
+  }
+}
+
+// low-bin partial sums of one y1: Ex bins l = 1..K (index l - 1), Ey bins l = 0..K
+template <int N1, int Y1, int... L>
+__device__ __forceinline__ void low_acc(cx (&ax)[kLowBins], cx (&ay)[kLowBins + 1], float vx,
+                                        float vy, std::integer_sequence<int, L...>) {
+  acc_tw<N1, 0>(ay[0], vy);
+  (acc_tw<N1, (L + 1) * Y1>(ax[L], vx), ...);
+  (acc_tw<N1, (L + 1) * Y1>(ay[L + 1], vy), ...);
+}
+
+// Loads of one y1 column of a row pair and its low-bin sums (x = N2 y1 + lane):
+// L[y, x] = Ex[y, x] - Ex[y, x-1] + Ey[y, x] - Ey[y-1, x] for rows y0 and y0 + 1. Elements
+// outside the image (x >= W, x - 1 < 0, rows outside [0, H), lanes j >= N2) read 0 through
+// out-of-range buffer offsets, so the code is straight-line and every load can be in flight
+// together.
+constexpr int kOOB = 0x70000000;  // a byte offset past every image (plans keep them < 2^30)
+
+// One slot per wavefront: the rows are uniform, each row gets its own descriptor whose
+// range is that row (empty outside the image), and x >= W falls outside it.
+struct PairRowsU {
+  rsrc_t x0, x1, ym, y0, y1;
+  int vb;  // lane * 4, or kOOB for lanes j >= N2
+};
+template <int N1, int N2, int Y1>
+__device__ __forceinline__ void pair_block(cx (&a)[N1], cx (&ax0)[kLowBins],
+                                           cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
+                                           cx (&ay1)[kLowBins + 1], const PairRowsU& r, int W) {
+  const int v = r.vb + N2 * Y1 * 4;
+  const float gx0 = bld1(r.x0, v, 0), gx0m = bld1(r.x0, v - 4, 0);
+  const float gx1 = bld1(r.x1, v, 0), gx1m = bld1(r.x1, v - 4, 0);
+  const float gym = bld1(r.ym, v, 0), gy0 = bld1(r.y0, v, 0), gy1 = bld1(r.y1, v, 0);
+  a[Y1] = {(gx0 - gx0m) + (gy0 - gym), (gx1 - gx1m) + (gy1 - gy0)};
+  low_acc<N1, Y1>(ax0, ay0, gx0, gy0, std::make_integer_sequence<int, kLowBins>{});
+  low_acc<N1, Y1>(ax1, ay1, gx1, gy1, std::make_integer_sequence<int, kLowBins>{});
+}
+
+// Several slots per wavefront: per-lane row offsets into image-wide descriptors (kOOB for
+// rows outside the image and lanes j >= N2), masked per y1 block at x >= W and x - 1 < 0.
+struct PairRowsL {
+  rsrc_t gx, gy;
+  int zm, z0, z1;   // byte offsets of (row, lane) for rows y0 - 1, y0, y0 + 1
+  int z0m, z1m;     // x - 1 at y1 = 0: kOOB for lane 0
+  int lane;
+};
+template <int N1, int N2, int Y1>
+__device__ __forceinline__ void pair_block(cx (&a)[N1], cx (&ax0)[kLowBins],
+                                           cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
+                                           cx (&ay1)[kLowBins + 1], const PairRowsL& r, int W) {
+  const int lim = W - N2 * Y1;  // x < W  <=>  lane < lim
+  const bool xin = r.lane < lim, xmin = r.lane <= lim;
+  constexpr int so = N2 * Y1 * 4, som = Y1 == 0 ? 0 : N2 * Y1 * 4 - 4;
+  const int o0 = xin ? r.z0 : kOOB, o1 = xin ? r.z1 : kOOB, om = xin ? r.zm : kOOB;
+  const int p0 = xmin ? (Y1 == 0 ? r.z0m : r.z0) : kOOB;
+  const int p1 = xmin ? (Y1 == 0 ? r.z1m : r.z1) : kOOB;
+  const float gx0 = bld1(r.gx, o0, so), gx0m = bld1(r.gx, p0, som);
+  const float gx1 = bld1(r.gx, o1, so), gx1m = bld1(r.gx, p1, som);
+  const float gym = bld1(r.gy, om, so), gy0 = bld1(r.gy, o0, so), gy1 = bld1(r.gy, o1, so);
+  a[Y1] = {(gx0 - gx0m) + (gy0 - gym), (gx1 - gx1m) + (gy1 - gy0)};
+  low_acc<N1, Y1>(ax0, ay0, gx0, gy0, std::make_integer_sequence<int, kLowBins>{});
+  low_acc<N1, Y1>(ax1, ay1, gx1, gy1, std::make_integer_sequence<int, kLowBins>{});
+}
+
+// blocks y1 < NB carry the support [0, W]; the rest of a[] is zero
+template <int N1, int N2, int NB, int Y1, class Rows>
+__device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
+                                          cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
+                                          cx (&ay1)[kLowBins + 1], const Rows& r, int W) {
+  if constexpr (Y1 < N1) {
+    if constexpr (Y1 < NB) pair_block<N1, N2, Y1>(a, ax0, ay0, ax1, ay1, r, W);
+    else a[Y1] = {0.f, 0.f};
+    pair_load<N1, N2, NB, Y1 + 1>(a, ax0, ay0, ax1, ay1, r, W);
+  }
+}
+
+template <int N1, int N2, int SLOTS, int NB>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) {
   using C = RowCfg<N1, N2>;
-  __shared__ float s_re[SLOTS][C::LDSC];
-  __shared__ float s_im[SLOTS][C::LDSC];
-  const int slot = threadIdx.x / C::G;
-  const int lane = threadIdx.x % C::G;
-  float* re = s_re[slot];
-  float* im = s_im[slot];
-  const int strip = bx * SLOTS + slot;
-  const bool strip_ok = strip < p.nstrips;
-  const int y0 = strip * p.strip;
-  const int K1 = p.KP;
-  const rsrc_t rgx = make_buf(p.gx + b * p.img_in, p.img_in * 4);
-  const rsrc_t rgy = make_buf(p.gy + b * p.img_in, p.img_in * 4);
+  constexpr int KL = kLowBins;
+  constexpr int NC = 2 * KL + 1;         // low-bin complex values per row
+  constexpr int NV = 4 * NC;             // floats per lane to sum: two rows, re and im
+  constexpr int RS = C::G + 1;           // LDS stride of one value over the lanes
+  constexpr int PLANE = cmax(C::LDSC, (NV * RS + 1) / 2);
+  __shared__ float s_lds[SLOTS][2 * PLANE];
+  const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
+  const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
+  float* re = s_lds[slot];
+  float* im = s_lds[slot] + PLANE;
+  const float* gxi = p.gx + b * p.img_in;
+  const float* gyi = p.gy + b * p.img_in;
   const rsrc_t rT1 = make_buf(p.T1 + b * p.img_t1, p.img_t1 * 8);
   const rsrc_t rSB = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
   const rsrc_t rtw = make_buf(p.twA, (long long)C::N * 8);
-  const rsrc_t rsx = make_buf(p.sx, (long long)C::NH * 8);
+  const rsrc_t rtl = make_buf(p.twL, (long long)2 * (KL + 1) * C::G * 8);
+  const rsrc_t rgx = make_buf(gxi, p.img_in * 4);
+  const rsrc_t rgy = make_buf(gyi, p.img_in * 4);
 
-  cx prev[C::NI];
-#pragma unroll
-  for (int i = 0; i < C::NI; ++i) prev[i] = {0.f, 0.f};
-
-  for (int it = 0; it <= p.strip; ++it) {
+  for (int r = 0; r < p.ppw; ++r) {
     const int tz = fresh_zero();
-    const int y = y0 - 1 + it;
-    const bool row_in = strip_ok && y >= 0 && y < p.H;
+    const int q = (bx * SLOTS + slot) * p.ppw + r;
+    const bool ok = q < p.npairs;
+    const int y0 = 2 * q;
     cx a[N1];
-    if (lane < N2) {
-      const int vo = (y * p.W + lane) * 4;
+    cx ax0[KL], ay0[KL + 1], ax1[KL], ay1[KL + 1];
 #pragma unroll
-      for (int y1 = 0; y1 < N1; ++y1) {
-        // tz keeps the bounds tests inside the row loop (hoisted, their masks spill)
-        const int x = N2 * y1 + lane + tz;
-        if (row_in && x < p.W) {
-          a[y1] = {bld1(rgx, vo, N2 * y1 * 4), bld1(rgy, vo, N2 * y1 * 4)};
-        } else {
-          a[y1] = {0.f, 0.f};
-        }
+    for (int l = 0; l < KL; ++l) ax0[l] = ax1[l] = {0.f, 0.f};
+#pragma unroll
+    for (int l = 0; l <= KL; ++l) ay0[l] = ay1[l] = {0.f, 0.f};
+    if constexpr (SLOTS == 1) {
+      auto row = [&](const float* img, int y) {
+        const bool in = ok && y >= 0 && y < p.H;
+        return make_buf(img + (in ? (long long)y * p.W : 0), in ? (long long)p.W * 4 : 0);
+      };
+      // tz: the per-y1 offsets are formed in the loop, not hoisted and held live
+      const PairRowsU rows{row(gxi, y0), row(gxi, y0 + 1), row(gyi, y0 - 1), row(gyi, y0),
+                           row(gyi, y0 + 1), (lane < N2 ? lane * 4 : kOOB) + tz};
+      pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W);
+    } else {
+      auto off = [&](int y) {
+        return (ok && lane < N2 && y >= 0 && y < p.H) ? (y * p.W + lane) * 4 : kOOB;
+      };
+      const int z0 = off(y0), z1 = off(y0 + 1);
+      const PairRowsL rows{rgx, rgy, off(y0 - 1), z0, z1,
+                           lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
+      pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W + tz);  // tz: masks per row pair
+    }
+
+    // lane factors w_N^(l j) (Ex also times 1 - w_N^l), then the sums over the lanes
+#pragma unroll
+    for (int l = 0; l <= KL; ++l) {
+      const f2b wy = bld2(rtl, lane * 8, tz + (KL + 1 + l) * C::G * 8);
+      if (l > 0) {
+        const f2b wx = bld2(rtl, lane * 8, tz + l * C::G * 8);
+        ax0[l - 1] = cmul(ax0[l - 1], cx{wx.x, wx.y});
+        ax1[l - 1] = cmul(ax1[l - 1], cx{wx.x, wx.y});
+        ay0[l] = cmul(ay0[l], cx{wy.x, wy.y});
+        ay1[l] = cmul(ay1[l], cx{wy.x, wy.y});
       }
     }
+    // value index: row r of the pair, complex index c < NC (Ex bins 1..K, then Ey bins 0..K)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const cx v0 = c < KL ? ax0[c < KL ? c : 0] : ay0[c < KL ? 0 : c - KL];
+      const cx v1 = c < KL ? ax1[c < KL ? c : 0] : ay1[c < KL ? 0 : c - KL];
+      re[(2 * c) * RS + lane] = v0.x;
+      re[(2 * c + 1) * RS + lane] = v0.y;
+      re[(2 * NC + 2 * c) * RS + lane] = v1.x;
+      re[(2 * NC + 2 * c + 1) * RS + lane] = v1.y;
+    }
+    slot_sync();
+    // lane t sums values t, t + G, ... over the N2 lanes that hold elements
+    constexpr int NVL = (NV + C::G - 1) / C::G;
+    float lowsum[NVL];
+#pragma unroll
+    for (int k = 0; k < NVL; ++k) {
+      lowsum[k] = 0.f;
+      const int v = lane + C::G * k;
+      if (v < NV) {
+#pragma unroll
+        for (int j = 0; j < N2; ++j) lowsum[k] += re[v * RS + j];
+      }
+    }
+    slot_sync();
+
     fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
-    const bool emit = strip_ok && it > 0 && y <= p.H;
+
+    // Z = FFT(L[y0] + i L[y0+1]): L^[y0, l] = (Z[l] + conj Z[N-l]) / 2,
+    // L^[y0+1, l] = (Z[l] - conj Z[N-l]) / 2i; bins l <= K come from the direct sums
+    const bool has1 = ok && y0 + 1 <= p.H;
 #pragma unroll
     for (int i = 0; i < C::NI; ++i) {
       const int l = lane + C::G * i;
-      if (l < C::NH) {
+      if (ok && l < C::NH && (l == 0 || l > KL)) {
         const int m = (l == 0) ? 0 : C::N - l;
         const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
-        const cx ex = {0.5f * (ar + br), 0.5f * (ai - bi)};
-        const cx ey = {0.5f * (ai + bi), 0.5f * (br - ar)};
-        if (emit) {
-          const f2b sv = bld2(rsx, lane * 8, tz + C::G * i * 8);
-          cx t = cmul(cx{sv.x, sv.y}, ex);
-          if (l > p.K) {
-            t = cadd(t, csub(ey, prev[i]));
-          } else if (y < p.H) {
-            bst2(rSB, ey.x, ey.y, (y * K1 + lane) * 8, C::G * i * 8);
-          }
-          bst2(rT1, t.x, t.y, (y * C::NHP + lane) * 8, C::G * i * 8);
+        cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
+        cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
+        if (l == 0) A = B = {0.f, 0.f};  // (1 - w_N^0) Ex^ = 0; Ey^ goes to SB
+        bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
+        if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NVL; ++k) {
+      const int v = lane + C::G * k;
+      if (ok && v < NV) {
+        const int rr = v / (2 * NC), c = (v / 2) % NC, comp = v & 1;
+        const int y = y0 + rr;
+        if (c < KL) {
+          if (y <= p.H) bst1(rT1, lowsum[k], (y * C::NHP + c + 1) * 8 + comp * 4, 0);
+        } else if (y < p.H) {
+          bst1(rSB, lowsum[k], (y * p.KP + c - KL) * 8 + comp * 4, 0);
         }
-        prev[i] = ey;
       }
     }
     slot_sync();
   }
 }
 
-template <int N1, int N2, int SLOTS>
+// NB: y1 blocks that can hold the support [0, W] (all N1, or N1/2 + 1 when 2 W <= N)
+template <int N1, int N2, int SLOTS, int NB>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_fwd(RowFwdArgs p) {
   int bx, by;
   xcd_contiguous(bx, by);
-  row_fwd_body<N1, N2, SLOTS>(p, bx, by);
+  row_fwd_body<N1, N2, SLOTS, NB>(p, bx, by);
 }
 
 // ragged batches: one work item (image, block) per workgroup; pointers rebased per image
-template <int N1, int N2, int SLOTS>
+template <int N1, int N2, int SLOTS, int NB>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
   const RgItem it = items[blockIdx.x];
@@ -225,7 +384,7 @@ k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
   p.gy = base.gy + e.in;
   p.T1 = reinterpret_cast<f2*>(base.ws + e.t);
   p.SB = reinterpret_cast<f2*>(base.ws + e.side);
-  row_fwd_body<N1, N2, SLOTS>(p, it.blk, 0);
+  row_fwd_body<N1, N2, SLOTS, NB>(p, it.blk, 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -402,29 +561,33 @@ k_row_binv(RowBwdInvArgs p) {
   const rsrc_t rsxm = make_buf(p.sxm, (long long)C::NH * 8);
   const int tz = fresh_zero();
 
+  // All loads first (branch-free: rows outside the image read 0 through an out-of-range
+  // offset, bins past NH are loaded and ignored), so they are in flight together.
+  constexpr int NID = (kLowBinsB + C::G) / C::G;  // slices that can hold a bin l <= Kb
+  const int ow0 = row_ok ? (y * C::NHP + lane) * 8 : kOOB;
+  const int ow1 = row_ok ? ((y + 1) * C::NHP + lane) * 8 : kOOB;
+  cx cur[C::NI], nxt[C::NI], smv[C::NI], sdv[NID];
+#pragma unroll
+  for (int i = 0; i < C::NI; ++i) {
+    const f2b v0 = bld2(rW, ow0, C::G * i * 8);
+    const f2b v1 = bld2(rW, ow1, C::G * i * 8);
+    const f2b sm = bld2(rsxm, lane * 8, tz + C::G * i * 8);
+    cur[i] = {v0.x, v0.y};
+    nxt[i] = {v1.x, v1.y};
+    smv[i] = {sm.x, sm.y};
+  }
+#pragma unroll
+  for (int i = 0; i < NID; ++i) {
+    const int l = lane + C::G * i;
+    const f2b v = bld2(rSD, (row_ok && l <= p.Kb) ? (y * Kb1 + l) * 8 : kOOB, 0);
+    sdv[i] = {v.x, v.y};
+  }
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) {
     const int l = lane + C::G * i;
+    const cx X1 = cmul(smv[i], cur[i]);
+    const cx X2 = (i < NID && l <= p.Kb) ? sdv[i < NID ? i : 0] : csub(cur[i], nxt[i]);
     if (l < C::NH) {
-      cx cur = {0.f, 0.f}, nxt = {0.f, 0.f};
-      if (row_ok) {
-        const f2b v0 = bld2(rW, (y * C::NHP + lane) * 8, C::G * i * 8);
-        const f2b v1 = bld2(rW, ((y + 1) * C::NHP + lane) * 8, C::G * i * 8);
-        cur = {v0.x, v0.y};
-        nxt = {v1.x, v1.y};
-      }
-      const f2b sm = bld2(rsxm, lane * 8, tz + C::G * i * 8);
-      const cx X1 = cmul(cx{sm.x, sm.y}, cur);
-      cx X2;
-      if (l <= p.Kb) {
-        X2 = {0.f, 0.f};
-        if (row_ok) {
-          const f2b v = bld2(rSD, (y * Kb1 + lane) * 8, C::G * i * 8);
-          X2 = {v.x, v.y};
-        }
-      } else {
-        X2 = csub(cur, nxt);
-      }
       // full spectrum of dgx + i dgy at bins l and N - l
       re[l] = X1.x - X2.y;
       im[l] = X1.y + X2.x;
@@ -464,9 +627,16 @@ struct RowLaunch {
   using C = RowCfg<N1, N2>;
   // 64-lane slots run one wavefront per workgroup; narrower slots fill 256-thread groups
   static constexpr int SLOTS = C::G == 64 ? 1 : 256 / C::G;
+  // y1 blocks of the forward loads: rows with 2 W <= N have their support in the first
+  // N1/2 + 1 of them
+  static constexpr int NB_HALF = N1 / 2 + 1 < N1 ? N1 / 2 + 1 : N1;
   static hipError_t fwd(const RowFwdArgs& a, int B, hipStream_t s) {
-    dim3 grid((a.nstrips + SLOTS - 1) / SLOTS, B);
-    hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
+    const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
+    dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
+    if (2 * a.W <= N1 * N2)
+      hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF>), grid, dim3(SLOTS * C::G), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t inv(const RowInvArgs& a, int B, hipStream_t s) {
@@ -486,10 +656,15 @@ struct RowLaunch {
     hipLaunchKernelGGL((k_row_binv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
+  // half: every image of the launch has 2 W <= N
   static hipError_t rg_fwd(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
-                           int nitems, hipStream_t s) {
-    hipLaunchKernelGGL((k_row_fwd_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
-                       base, tab, items);
+                           int nitems, bool half, hipStream_t s) {
+    if (half)
+      hipLaunchKernelGGL((k_row_fwd_rg<N1, N2, SLOTS, NB_HALF>), dim3(nitems),
+                         dim3(SLOTS * C::G), 0, s, base, tab, items);
+    else
+      hipLaunchKernelGGL((k_row_fwd_rg<N1, N2, SLOTS, N1>), dim3(nitems), dim3(SLOTS * C::G),
+                         0, s, base, tab, items);
     return hipGetLastError();
   }
   static hipError_t rg_inv(const RgBase& base, const RgRowInv* tab, const RgItem* items,
