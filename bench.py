@@ -41,8 +41,11 @@ def stage_model(H, W, N, K, Kb, kind):
     NH = N // 2 + 1
     fft = 5.0 * N * math.log2(N)
     if kind == "fwd":
+        # row pass: two divergence rows per complex FFT, plus direct sums of the K + 1
+        # lowest bins of Ex and Ey (2K + 1 complex bins, W real samples, 4 flops each)
         return {
-            "k_row_fwd": (8.0 * H * W + 8.0 * (H + 1) * NH + 8.0 * H * (K + 1), (H + 1) * fft),
+            "k_row_fwd": (8.0 * H * W + 8.0 * (H + 1) * NH + 8.0 * H * (K + 1),
+                          math.ceil((H + 1) / 2) * fft + 4.0 * H * W * (2 * K + 1)),
             "k_col_fwd": (8.0 * (H + 1) * NH + 8.0 * H * (K + 1) + 8.0 * H * NH, 0.0),
             "k_row_inv": (8.0 * H * NH + 4.0 * H * W, math.ceil(H / 2) * fft),
         }
@@ -171,6 +174,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--no-color", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -256,7 +260,8 @@ def main():
     stage_ms = {n: sum(ev[i][k].elapsed_time(ev[i][k + 1]) for i in range(args.steps)) / args.steps
                 for k, n in enumerate(names)}
 
-    model = stage_model(H, W_, w.N, min(16, w.N // 2), min(64, w.N // 2), "fwd")
+    K, Kb = plan.get_param("low_bins"), plan.get_param("low_bins_b")
+    model = stage_model(H, W_, w.N, K, Kb, "fwd")
     dom = max(stage_ms, key=stage_ms.get)
     bytes_dom = model[dom][0] * B
     flops_dom = model[dom][1] * B
@@ -286,6 +291,33 @@ def main():
         "path_hbm_frac": total_bytes / (ms_step / 1e3) / HBM_PEAK,
         "roofline": roof,
     }
+
+    if not args.no_color:
+        # forward solve + colour correction of eq. (25): one more read and write of u
+        means = torch.full((B,), 0.5, device=dev)
+        stds = torch.full((B,), 0.2, device=dev)
+
+        def color_step():
+            st = L.gfc_solve_batch_color(hp, gx.data_ptr(), gy.data_ptr(), means.data_ptr(),
+                                         stds.data_ptr(), u.data_ptr(), B, ws.data_ptr(),
+                                         ws.numel(), sp)
+            if st != 0:
+                raise gfc.GFCError(st, "gfc_solve_batch_color")
+
+        for _ in range(args.warmup):
+            color_step()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0.record(stream)
+        for _ in range(args.steps):
+            color_step()
+        c1.record(stream)
+        torch.cuda.synchronize()
+        ms_c = c0.elapsed_time(c1) / args.steps
+        result["color"] = {"solves_per_s": B / (ms_c / 1e3), "ms_per_step": ms_c,
+                           "over_plain": ms_c / ms_step,
+                           "statistics": "source mean 0.5 and std 0.2 for every image"}
 
     if not args.no_bwd:
         du = torch.randn_like(gx) * 0.1
@@ -322,7 +354,7 @@ def main():
         ms_pair = t0.elapsed_time(t1) / nb
         bms = {n: sum(evb[i][k].elapsed_time(evb[i][k + 1]) for i in range(nb)) / nb
                for k, n in enumerate(names_b)}
-        mb = stage_model(H, W_, w.N, 16, min(64, w.N // 2), "bwd")
+        mb = stage_model(H, W_, w.N, K, Kb, "bwd")
         result["fwd_bwd"] = {"pairs_per_s": B / (ms_pair / 1e3), "ms_per_pair_step": ms_pair,
                              "stages_ms": {k: round(v, 5) for k, v in bms.items()},
                              "bwd_hbm_frac": sum(v[0] for v in mb.values()) * B /

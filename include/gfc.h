@@ -82,6 +82,9 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream);
  *   "col_c"     1..64   (power of two) columns per workgroup in the column pass
  *   "col_rows"  16|32   rows per thread in the column pass
  * The project's autotuner chooses these per (H, W, M, N); host-only.
+ * gfc_plan_get_param also reads two fixed values: "low_bins" (K: row frequencies l <= K
+ * reach the forward column pass as the x- and y-parts of the divergence separately) and
+ * "low_bins_b" (Kb: backward columns l <= Kb take -D_y inside the column recursion).
  */
 gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value);
 gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value);
@@ -100,6 +103,19 @@ gfc_status gfc_workspace_size(gfc_plan_t p, int B, size_t* bytes);
  */
 gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float* u, int B,
                            void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Forward solve followed by the colour-preserving correction of eq. (25) (Sec. 3.2.2):
+ *   u = (u_c - mean(u_c)) * I_std[b] / std(u_c) + I_mean[b]   over each H x W image,
+ * where u_c is what gfc_solve_batch returns and I_mean, I_std ([B] float32, device) are the
+ * mean and the population standard deviation of each source image I. The statistics of
+ * u_c are float64 sums taken by the inverse row pass in a fixed order (deterministic); a
+ * constant u_c (std 0) maps to I_mean. One more read and write of u than gfc_solve_batch.
+ * Workspace as for gfc_solve_batch (gfc_workspace_size covers both).
+ */
+gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
+                                 const float* I_mean, const float* I_std, float* u, int B,
+                                 void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Backward (adjoint) of gfc_solve_batch, for using the solver as a differentiable layer

@@ -39,7 +39,7 @@ import scipy.fft as sfft
 __all__ = [
     "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_algorithm_a",
     "embed", "divergence", "solve_fft", "solve_direct", "lstsq_torus", "torus_gradient",
-    "solve_backward", "green_function", "cpu_workers",
+    "solve_backward", "green_function", "cpu_workers", "color_correct",
 ]
 
 
@@ -214,3 +214,26 @@ def solve_backward(du, M: int, N: int, workers: int | None = None):
     if single:
         return dgx[0], dgy[0]
     return dgx, dgy
+
+
+def color_correct(u, I_mean, I_std) -> np.ndarray:
+    """Colour-preserving correction of eq. (25), per image over its H x W crop:
+        I_corr = (I_c - mean(I_c)) * sigma(I) / sigma(I_c) + mean(I).
+    u: [..., H, W] solved images I_c; I_mean, I_std: mean and standard deviation of each
+    source image I (one value per leading index). sigma is the population standard
+    deviation. The ratio sigma(I) / sigma(I_c) is the same for any normalisation common to
+    both (n or n - 1), so only I_std has to use the same one. Where the paper is silent: a
+    constant I_c (sigma(I_c) = 0) has no contrast to rescale, and its output is mean(I)."""
+    u = np.asarray(u, dtype=np.float64)
+    flat = u.reshape(-1, u.shape[-2] * u.shape[-1])
+    means = np.asarray(I_mean, dtype=np.float64).reshape(-1)
+    stds = np.asarray(I_std, dtype=np.float64).reshape(-1)
+    if means.size != flat.shape[0] or stds.size != flat.shape[0]:
+        raise ValueError("one mean and one standard deviation per image")
+    out = np.empty_like(flat)
+    for i in range(flat.shape[0]):
+        mu = flat[i].mean()
+        sd = np.sqrt(np.mean((flat[i] - mu) ** 2))
+        ratio = stds[i] / sd if sd > 0 else 0.0
+        out[i] = (flat[i] - mu) * ratio + means[i]
+    return out.reshape(u.shape)

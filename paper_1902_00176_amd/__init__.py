@@ -57,6 +57,7 @@ def lib():
             L.gfc_workspace_size.argtypes = [vp, i, ctypes.POINTER(sz)]
             L.gfc_solve_batch.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_solve_batch_color.argtypes = [vp, vp, vp, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_batch_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_plan_set_param.argtypes = [vp, ctypes.c_char_p, i]
@@ -253,6 +254,30 @@ class Plan:
                                          _stream_ptr(torch, dev, stream)), "gfc_solve_batch")
         return u
 
+    def solve_color(self, gx, gy, I_mean, I_std, out=None, workspace=None, stream=None):
+        """Solve, then the colour-preserving correction of eq. (25): each image is rescaled
+        to the mean I_mean and population standard deviation I_std of its source image
+        (float32 tensors with one value per image, on the same device)."""
+        torch, dev = self._prep(gx, gy)
+        if gx.shape != gy.shape:
+            raise ValueError("gx and gy must have the same shape")
+        gx = gx.contiguous()
+        gy = gy.contiguous()
+        B = gx.numel() // (self.H * self.W)
+        I_mean = torch.as_tensor(I_mean, dtype=torch.float32, device=dev).reshape(-1).contiguous()
+        I_std = torch.as_tensor(I_std, dtype=torch.float32, device=dev).reshape(-1).contiguous()
+        if I_mean.numel() != B or I_std.numel() != B:
+            raise ValueError(f"expected {B} means and standard deviations")
+        u = out if out is not None else torch.empty_like(gx)
+        ws = self._workspace(torch, dev, B, workspace)
+        with torch.cuda.device(dev):
+            _check(lib().gfc_solve_batch_color(
+                self._h, gx.data_ptr(), gy.data_ptr(), I_mean.data_ptr(), I_std.data_ptr(),
+                u.data_ptr(), B, ws.data_ptr() if ws is not None else None,
+                ws.numel() if ws is not None else 0, _stream_ptr(torch, dev, stream)),
+                "gfc_solve_batch_color")
+        return u
+
     def backward(self, du, workspace=None, stream=None):
         torch, dev = self._prep(du)
         du = du.contiguous()
@@ -295,6 +320,12 @@ def get_plan(H: int, W: int, M: int = 0, N: int = 0) -> Plan:
 def solve(gx, gy, M: int = 0, N: int = 0, **kw):
     """u = GFC(gx, gy) for float32 CUDA tensors of shape [..., H, W]."""
     return get_plan(gx.shape[-2], gx.shape[-1], M or 0, N or 0).solve(gx, gy, **kw)
+
+
+def solve_color(gx, gy, I_mean, I_std, M: int = 0, N: int = 0, **kw):
+    """GFC(gx, gy) with the colour correction of eq. (25) to the source statistics."""
+    return get_plan(gx.shape[-2], gx.shape[-1], M or 0, N or 0).solve_color(gx, gy, I_mean,
+                                                                            I_std, **kw)
 
 
 def solve_backward(du, M: int = 0, N: int = 0, **kw):

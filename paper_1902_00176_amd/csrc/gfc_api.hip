@@ -228,6 +228,8 @@ gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
   else if (!std::strcmp(name, "row_ppw")) *value = p->row_ppw;
   else if (!std::strcmp(name, "col_c")) *value = p->gf.C;
   else if (!std::strcmp(name, "col_rows")) *value = p->col_rows;
+  else if (!std::strcmp(name, "low_bins")) *value = p->K;
+  else if (!std::strcmp(name, "low_bins_b")) *value = p->Kb;
   else return GFC_E_ARG;
   return GFC_OK;
 }
@@ -363,6 +365,34 @@ gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float
   if (!p->built) return GFC_E_NOT_BUILT;
   if (B == 0) return GFC_OK;
   return gfc_solve_batch_stage(p, 0, gx, gy, u, B, workspace, ws_bytes, stream);
+}
+
+gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
+                                 const float* I_mean, const float* I_std, float* u, int B,
+                                 void* workspace, size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!workspace || !gx || !gy || !u || !I_mean || !I_std) return GFC_E_ARG;
+  const WsLayout w = ws_layout(p, B);
+  if (ws_bytes < w.total) return GFC_E_WORKSPACE;
+  auto* ws = static_cast<unsigned char*>(workspace);
+  f2* T = reinterpret_cast<f2*>(ws + w.t);
+  f2* SB = reinterpret_cast<f2*>(ws + w.side);
+  double* partial = reinterpret_cast<double*>(ws + w.red);
+  double* mom = reinterpret_cast<double*>(ws + w.mom);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  gfc_status st = hip_status(p->rk->fwd(row_fwd_args(p, gx, gy, T, SB), B, s));
+  if (st != GFC_OK) return st;
+  st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s, p->side, p->ev_fork,
+                                 p->ev_join));
+  if (st != GFC_OK) return st;
+  RowInvArgs v = row_inv_args(p, T, u, partial);
+  v.mom = mom;
+  st = hip_status(p->rk->inv(v, B, s));
+  if (st != GFC_OK) return st;
+  return hip_status(launch_color_apply(u, mom, inv_groups(p), I_mean, I_std,
+                                       (long long)p->H * p->W, B, s));
 }
 
 gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, float* dgx,

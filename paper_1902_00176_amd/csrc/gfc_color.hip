@@ -1,0 +1,62 @@
+// gfc_color.hip - colour-preserving correction of eq. (25):
+//     I_corr = (I_c - mean(I_c)) * sigma(I) / sigma(I_c) + mean(I),
+// applied in place to the solved images. The inverse row pass leaves float64 sums of u and
+// u^2 per workgroup; here every workgroup of an image reduces that image's sums in one fixed
+// order (so all of them derive bit-identical statistics), then rescales its share of the
+// pixels. sigma is the population standard deviation; the caller's sigma(I) must use the
+// same normalisation. A constant image (sigma(I_c) = 0) maps to mean(I).
+#include "gfc_buf.h"
+#include "gfc_internal.h"
+
+namespace gfc {
+
+constexpr int kColorThreads = 256;
+constexpr int kColorPerThread = 16;  // pixels per thread: a workgroup covers 4096
+
+__global__ void __launch_bounds__(kColorThreads)
+k_color_apply(float* u, const double* mom, int nparts, const float* I_mean, const float* I_std,
+              long long npix) {
+  __shared__ double s1[kColorThreads], s2[kColorThreads];
+  const int b = blockIdx.y;
+  const int t = threadIdx.x;
+  double a1 = 0.0, a2 = 0.0;
+  for (int j = t; j < nparts; j += kColorThreads) {
+    a1 += mom[2 * ((long long)b * nparts + j)];
+    a2 += mom[2 * ((long long)b * nparts + j) + 1];
+  }
+  s1[t] = a1;
+  s2[t] = a2;
+  __syncthreads();
+  for (int h = kColorThreads / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      s1[t] += s1[t + h];
+      s2[t] += s2[t + h];
+    }
+    __syncthreads();
+  }
+  const double n = double(npix);
+  const double mean = s1[0] / n;
+  const double var = s2[0] / n - mean * mean;
+  const double sd = var > 0.0 ? __builtin_sqrt(var) : 0.0;
+  const float ratio = sd > 0.0 ? float(double(I_std[b]) / sd) : 0.0f;
+  const float mf = float(mean), im = I_mean[b];
+  const rsrc_t r = make_buf(u + b * npix, npix * 4);
+  const int base = blockIdx.x * kColorThreads * kColorPerThread + t;
+  float v[kColorPerThread];
+#pragma unroll
+  for (int k = 0; k < kColorPerThread; ++k) v[k] = bld1(r, (base + k * kColorThreads) * 4, 0);
+#pragma unroll
+  for (int k = 0; k < kColorPerThread; ++k)
+    bst1(r, __builtin_fmaf(v[k] - mf, ratio, im), (base + k * kColorThreads) * 4, 0);
+}
+
+hipError_t launch_color_apply(float* u, const double* mom, int nparts, const float* I_mean,
+                              const float* I_std, long long npix, int B, hipStream_t s) {
+  const long long per = (long long)kColorThreads * kColorPerThread;
+  dim3 grid(unsigned((npix + per - 1) / per), B);
+  hipLaunchKernelGGL(k_color_apply, grid, dim3(kColorThreads), 0, s, u, mom, nparts, I_mean,
+                     I_std, npix);
+  return hipGetLastError();
+}
+
+}  // namespace gfc

@@ -40,7 +40,13 @@ struct RowInvArgs {
   int npairs;         // ceil(H / 2)
   int ppw;            // row pairs per slot
   long long img_t2, img_u;
+  double* mom;        // [B][gridDim.x][2]: sums of u and u^2 per workgroup, or null
 };
+
+// Colour correction of eq. (25) in place on u [B][npix]: every workgroup of image b reduces
+// that image's nparts moment pairs in a fixed order, then u <- (u - mean) * I_std[b] / std + I_mean[b].
+hipError_t launch_color_apply(float* u, const double* mom, int nparts, const float* I_mean,
+                              const float* I_std, long long npix, int B, hipStream_t s);
 
 // Backward row pass 1: R2C of du rows (two rows per complex FFT), U[y, l], l in [0, NH);
 // also per-block partial sums of du for sum(du).

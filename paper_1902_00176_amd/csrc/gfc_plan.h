@@ -47,9 +47,16 @@ struct gfc_plan_s {
 
 namespace gfc {
 
-// workspace of a batch: spectra T, side arrays (SB forward / SD backward), reductions
+// workgroups of the inverse row pass (one moment pair each for the colour correction)
+inline int inv_groups(const gfc_plan_s* p) {
+  const int slots_needed = ((p->H + 1) / 2 + p->row_ppw - 1) / p->row_ppw;
+  return (slots_needed + p->rk->slots - 1) / p->rk->slots;
+}
+
+// workspace of a batch: spectra T, side arrays (SB forward / SD backward), reductions,
+// moment sums of the colour correction
 struct WsLayout {
-  size_t t, side, red, total;
+  size_t t, side, red, mom, total;
 };
 inline WsLayout ws_layout(const gfc_plan_s* p, int B) {
   WsLayout w{};
@@ -59,10 +66,12 @@ inline WsLayout ws_layout(const gfc_plan_s* p, int B) {
   const size_t sd = Bz * size_t(p->H) * p->KbP * sizeof(f2);
   const size_t pf = Bz * size_t(p->ntiles_f) * sizeof(double);
   const size_t ps = Bz * size_t(p->nsums) * sizeof(double);
+  const size_t pm = Bz * size_t(inv_groups(p)) * 2 * sizeof(double);
   w.t = 0;
   w.side = align256(tbytes);
   w.red = w.side + align256(std::max(sb, sd));
-  w.total = w.red + align256(std::max(pf, ps));
+  w.mom = w.red + align256(std::max(pf, ps));
+  w.total = w.mom + align256(pm);
   return w;
 }
 
@@ -125,6 +134,7 @@ inline RowInvArgs row_inv_args(const gfc_plan_s* p, const f2* T, float* u,
   v.ppw = p->row_ppw;
   v.img_t2 = (long long)(p->H + 1) * p->NHP;
   v.img_u = (long long)p->H * p->W;
+  v.mom = nullptr;
   return v;
 }
 

@@ -390,11 +390,15 @@ k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
 // ---------------------------------------------------------------------------------------
 // Inverse row pass (row C2R of eq. (23), real part, crop and Algorithm B's constant).
 // Each slot handles p.ppw pairs of rows, two rows per complex inverse FFT.
-template <int N1, int N2, int SLOTS>
+// MOM: also the float64 sums of the stored values and their squares, one pair per
+// workgroup (fixed summation order), for the colour correction of eq. (25).
+template <int N1, int N2, int SLOTS, bool MOM = false>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
+  __shared__ double s_mom[SLOTS][2];
+  double m1 = 0.0, m2 = 0.0;
   const int slot = threadIdx.x / C::G;
   const int lane = threadIdx.x % C::G;
   float* re = s_re[slot];
@@ -438,19 +442,47 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) 
       for (int j1 = 0; j1 < N1; ++j1) {
         const int x = lane + N2 * j1 + tz;  // tz: bounds tests stay inside the loop
         if (x < p.W) {
-          bst1(ru, a[j1].x - vref, v1, N2 * j1 * 4);
-          if (has2) bst1(ru, a[j1].y - vref, v2, N2 * j1 * 4);
+          const float o1 = a[j1].x - vref, o2 = a[j1].y - vref;
+          bst1(ru, o1, v1, N2 * j1 * 4);
+          if (has2) bst1(ru, o2, v2, N2 * j1 * 4);
+          if constexpr (MOM) {
+            const double d1 = o1, d2 = has2 ? double(o2) : 0.0;
+            m1 += d1 + d2;
+            m2 = __builtin_fma(d1, d1, __builtin_fma(d2, d2, m2));
+          }
         }
       }
     }
     slot_sync();
   }
+  if constexpr (MOM) {
+#pragma unroll
+    for (int off = C::G / 2; off > 0; off >>= 1) {
+      m1 += __shfl_xor(m1, off, C::G);
+      m2 += __shfl_xor(m2, off, C::G);
+    }
+    if (lane == 0) {
+      s_mom[slot][0] = m1;
+      s_mom[slot][1] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t1 = 0.0, t2 = 0.0;
+      for (int i = 0; i < SLOTS; ++i) {
+        t1 += s_mom[i][0];
+        t2 += s_mom[i][1];
+      }
+      double* o = p.mom + 2 * ((long long)b * gridDim.x + bx);
+      o[0] = t1;
+      o[1] = t2;
+    }
+  }
 }
 
-template <int N1, int N2, int SLOTS>
+template <int N1, int N2, int SLOTS, bool MOM>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_inv(RowInvArgs p) {
-  row_inv_body<N1, N2, SLOTS>(p, blockIdx.x, blockIdx.y);
+  row_inv_body<N1, N2, SLOTS, MOM>(p, blockIdx.x, blockIdx.y);
 }
 
 template <int N1, int N2, int SLOTS>
@@ -642,7 +674,10 @@ struct RowLaunch {
   static hipError_t inv(const RowInvArgs& a, int B, hipStream_t s) {
     const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
-    hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
+    if (a.mom)
+      hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS, true>), grid, dim3(SLOTS * C::G), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS, false>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t bfwd(const RowBwdFwdArgs& a, int B, hipStream_t s) {

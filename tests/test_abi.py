@@ -111,3 +111,20 @@ def test_ragged_create_host_logic():
     assert L.gfc_ragged_workspace_size(h, ctypes.byref(n)) == 3  # not built
     assert L.gfc_ragged_solve(h, None, None, None, None, 0, None) == 3
     L.gfc_ragged_destroy(h)
+
+
+def test_plan_parameters_round_trip_and_fixed_low_bins():
+    """Launch parameters are set and read back on the host; out-of-range values and unknown
+    names are rejected; K and Kb are read-only values of the plan."""
+    p = gfc.Plan(801, 1200, params={"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32},
+                 tuned=False)
+    assert p.params == {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32}
+    assert p.get_param("low_bins") == 4
+    assert p.get_param("low_bins_b") == 64
+    L = gfc.lib()
+    for name, value in (("row_fppw", 0), ("row_fppw", 65), ("col_c", 3), ("col_rows", 24),
+                        ("low_bins", 8), ("row_strip", 4)):
+        assert L.gfc_plan_set_param(p.handle, name.encode(), value) == 1, (name, value)
+    # a short row: Kb is capped by the half spectrum
+    q = gfc.Plan(5, 6, 12, 16)
+    assert q.get_param("low_bins") == 4 and q.get_param("low_bins_b") == 8

@@ -360,3 +360,47 @@ def test_planted_oracle_mistakes_are_caught(monkeypatch, mutation):
     a = _rand_field(rng, H, W)
     ls_ok = np.max(np.abs(G.solve_fft(*a, M, N) - G.lstsq_torus(*a, M, N))) < 1e-11
     assert not (framed_ok and ls_ok), f"mutation {mutation} went unnoticed"
+
+
+# ---------------------------------------------------------------- colour correction (eq. (25))
+
+def test_color_correction_restores_source_statistics():
+    """Eq. (25) maps each solved image onto the mean and standard deviation of its source."""
+    rng = np.random.default_rng(2501)
+    u = rng.normal(size=(3, 17, 23)) * np.array([0.5, 2.0, 7.0])[:, None, None] + 3.0
+    m = np.array([0.2, 0.5, -1.0])
+    s = np.array([0.1, 0.3, 2.5])
+    out = O.color_correct(u, m, s)
+    for i in range(3):
+        assert abs(out[i].mean() - m[i]) < 1e-13
+        assert abs(out[i].std() - s[i]) < 1e-13 * max(1.0, s[i])
+
+
+@pytest.mark.parametrize("k", [1.0, 0.25, 3.0])
+def test_color_correction_undoes_a_uniform_gradient_scale(k):
+    """Sec. 3.2.2: the sigma ratio only changes the norm of the gradient by a constant factor.
+    A framed image S whose gradient is scaled by k > 0 solves to k S (eq. (23)); the
+    correction with S's own statistics returns S exactly (k = 1 is the paper's unperturbed
+    case, I_corr = I_c)."""
+    rng = np.random.default_rng(int(k * 100))
+    H, W, M, N = 20, 31, 40, 64
+    S, gx, gy = _framed_conservative(rng, H, W)
+    u = O.solve_fft(k * gx, k * gy, M, N)
+    out = O.color_correct(u + 5.0, S.mean(), S.std())
+    assert np.max(np.abs(out - S)) < 1e-12
+
+
+def test_color_correction_is_invariant_to_positive_affine_maps():
+    rng = np.random.default_rng(2503)
+    u = rng.normal(size=(2, 9, 11))
+    m, s = np.array([0.4, 0.6]), np.array([0.2, 0.05])
+    ref = O.color_correct(u, m, s)
+    assert np.max(np.abs(O.color_correct(4.0 * u - 7.0, m, s) - ref)) < 1e-13
+    # a negative scale flips the image: the correction keeps the sign of the contrast
+    flipped = O.color_correct(-u, m, s)
+    assert np.max(np.abs((flipped - m[:, None, None]) + (ref - m[:, None, None]))) < 1e-13
+
+
+def test_color_correction_of_a_constant_image_is_the_source_mean():
+    out = O.color_correct(np.full((1, 4, 5), 3.0), [0.7], [0.2])
+    assert np.all(out == 0.7)
