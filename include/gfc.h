@@ -118,6 +118,29 @@ gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
                                  void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Gradient-domain editing in one call (Sec. 3.2): an edit of the gradient field, applied on
+ * the device to each pixel as it is loaded, then the forward solve, then optionally the
+ * colour correction of eq. (25).
+ *   mode GFC_EDIT_THRESHOLD (Sec. 3.2.3): param = tau >= 0. A pixel's gradient is kept
+ *     where fl(fl(gx*gx) + fl(gy*gy)) >= fl(tau*tau) (float32, in this order) and set to 0
+ *     elsewhere. The paper thresholds at 10% of the highest possible gradient: tau is that
+ *     absolute level. C is not read (may be NULL).
+ *   mode GFC_EDIT_GDM (eq. (26)): param = alpha in [0, 1]; C [B][H][W] float32 >= 0 is the
+ *     edge intensity. |E_p| = |E|^(1-alpha) * C^alpha with the orientation of E (float32
+ *     log2/exp2); E_p = 0 where E = 0.
+ *   I_mean, I_std: both NULL (no correction) or both [B] device arrays as for
+ *     gfc_solve_batch_color.
+ * GFC_E_ARG for an unknown mode, a parameter out of range, a missing C for GDM or only one
+ * of I_mean, I_std. Workspace as for gfc_solve_batch. The edited field itself is never
+ * stored; gx, gy and C are not modified.
+ */
+#define GFC_EDIT_THRESHOLD 1
+#define GFC_EDIT_GDM 2
+gfc_status gfc_solve_edit(gfc_plan_t p, const float* gx, const float* gy, const float* C,
+                          int mode, float param, const float* I_mean, const float* I_std,
+                          float* u, int B, void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Backward (adjoint) of gfc_solve_batch, for using the solver as a differentiable layer
  * (Sec. 4): given du = dLoss/du [B][H][W], writes dgx = dLoss/dgx and dgy = dLoss/dgy:
  *   r = embed(du) - sum(du) * delta_(0,0);  w = g (*) r;

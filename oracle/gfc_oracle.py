@@ -39,7 +39,8 @@ import scipy.fft as sfft
 __all__ = [
     "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_algorithm_a",
     "embed", "divergence", "solve_fft", "solve_direct", "lstsq_torus", "torus_gradient",
-    "solve_backward", "green_function", "cpu_workers", "color_correct",
+    "solve_backward", "green_function", "cpu_workers", "color_correct", "threshold_edit",
+    "gdm_edit",
 ]
 
 
@@ -237,3 +238,37 @@ def color_correct(u, I_mean, I_std) -> np.ndarray:
         ratio = stds[i] / sd if sd > 0 else 0.0
         out[i] = (flat[i] - mu) * ratio + means[i]
     return out.reshape(u.shape)
+
+
+def threshold_edit(gx, gy, tau: float):
+    """Gradient thresholding of Sec. 3.2.3: the gradient E = (gx, gy) of a pixel is kept
+    where its magnitude reaches tau and set to 0 elsewhere, which removes texture and fine
+    elements and keeps strong edges. The paper thresholds at 10% of the highest possible
+    gradient; here tau is that absolute level, chosen by the caller.
+
+    The keep/drop decision is an integer outcome of floating-point arithmetic, so it is taken
+    in float32, the precision of the inputs and of the GPU path, in this order:
+    m = fl(fl(gx*gx) + fl(gy*gy)) compared with t = fl(tau*tau) (tau rounded to float32
+    first), keep when m >= t. The kept values are exact."""
+    gx = np.asarray(gx, dtype=np.float32)
+    gy = np.asarray(gy, dtype=np.float32)
+    t = np.float32(np.float32(tau) * np.float32(tau))
+    m = (gx * gx) + (gy * gy)  # float32 products and sum, each rounded once
+    keep = m >= t
+    return (np.where(keep, gx, np.float32(0)).astype(np.float64),
+            np.where(keep, gy, np.float32(0)).astype(np.float64))
+
+
+def gdm_edit(gx, gy, C, alpha: float):
+    """Gradient domain merging, eq. (26): the perturbed field keeps the orientation of E and
+    takes the weighted geometric mean of the magnitudes, |E_p| = |E|^(1-alpha) * C^alpha, with
+    C >= 0 the edge intensity of each pixel and alpha in [0, 1]. Where |E| = 0 the orientation
+    is undefined and E_p = 0 (the paper is silent there). float64."""
+    gx = np.asarray(gx, dtype=np.float64)
+    gy = np.asarray(gy, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    mag = np.hypot(gx, gy)
+    nz = mag > 0
+    safe = np.where(nz, mag, 1.0)
+    scale = np.where(nz, safe ** (-alpha) * C ** alpha, 0.0)
+    return gx * scale, gy * scale

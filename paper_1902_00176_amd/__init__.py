@@ -58,6 +58,8 @@ def lib():
             L.gfc_solve_batch.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward.argtypes = [vp, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_batch_color.argtypes = [vp, vp, vp, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_solve_edit.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, vp, vp, vp, i, vp,
+                                         sz, vp]
             L.gfc_solve_batch_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_plan_set_param.argtypes = [vp, ctypes.c_char_p, i]
@@ -278,6 +280,39 @@ class Plan:
                 "gfc_solve_batch_color")
         return u
 
+    def solve_edit(self, gx, gy, mode: str, param: float, C=None, I_mean=None, I_std=None,
+                   out=None, workspace=None, stream=None):
+        """Edit the gradient on the device, solve, and optionally correct colours (eq. (25)).
+        mode "threshold": param = tau (keep |E| >= tau, Sec. 3.2.3); mode "gdm": param =
+        alpha with edge map C (eq. (26))."""
+        modes = {"threshold": EDIT_THRESHOLD, "gdm": EDIT_GDM}
+        if mode not in modes:
+            raise ValueError(f"unknown edit mode {mode!r}")
+        ts = [gx, gy] + ([C] if C is not None else [])
+        torch, dev = self._prep(*ts)
+        if gx.shape != gy.shape or (C is not None and C.shape != gx.shape):
+            raise ValueError("gx, gy and C must have the same shape")
+        gx, gy = gx.contiguous(), gy.contiguous()
+        C = C.contiguous() if C is not None else None
+        B = gx.numel() // (self.H * self.W)
+        stats = []
+        for t in (I_mean, I_std):
+            if t is not None:
+                t = torch.as_tensor(t, dtype=torch.float32, device=dev).reshape(-1).contiguous()
+                if t.numel() != B:
+                    raise ValueError(f"expected {B} means and standard deviations")
+            stats.append(t)
+        u = out if out is not None else torch.empty_like(gx)
+        ws = self._workspace(torch, dev, B, workspace)
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        with torch.cuda.device(dev):
+            _check(lib().gfc_solve_edit(
+                self._h, gx.data_ptr(), gy.data_ptr(), ptr(C), modes[mode], float(param),
+                ptr(stats[0]), ptr(stats[1]), u.data_ptr(), B, ptr(ws),
+                ws.numel() if ws is not None else 0, _stream_ptr(torch, dev, stream)),
+                "gfc_solve_edit")
+        return u
+
     def backward(self, du, workspace=None, stream=None):
         torch, dev = self._prep(du)
         du = du.contiguous()
@@ -326,6 +361,17 @@ def solve_color(gx, gy, I_mean, I_std, M: int = 0, N: int = 0, **kw):
     """GFC(gx, gy) with the colour correction of eq. (25) to the source statistics."""
     return get_plan(gx.shape[-2], gx.shape[-1], M or 0, N or 0).solve_color(gx, gy, I_mean,
                                                                             I_std, **kw)
+
+
+EDIT_THRESHOLD = 1
+EDIT_GDM = 2
+
+
+def solve_edit(gx, gy, mode, param, C=None, I_mean=None, I_std=None, M: int = 0, N: int = 0,
+               **kw):
+    """Gradient-domain editing: device-side edit (threshold or GDM), solve, optional eq. (25)."""
+    return get_plan(gx.shape[-2], gx.shape[-1], M or 0, N or 0).solve_edit(
+        gx, gy, mode, param, C=C, I_mean=I_mean, I_std=I_std, **kw)
 
 
 def solve_backward(du, M: int = 0, N: int = 0, **kw):

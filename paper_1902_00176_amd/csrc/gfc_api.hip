@@ -367,13 +367,12 @@ gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float
   return gfc_solve_batch_stage(p, 0, gx, gy, u, B, workspace, ws_bytes, stream);
 }
 
-gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
-                                 const float* I_mean, const float* I_std, float* u, int B,
-                                 void* workspace, size_t ws_bytes, void* stream) {
-  if (!p || B < 0) return GFC_E_ARG;
-  if (!p->built) return GFC_E_NOT_BUILT;
-  if (B == 0) return GFC_OK;
-  if (!workspace || !gx || !gy || !u || !I_mean || !I_std) return GFC_E_ARG;
+// forward solve with an optional gradient edit before the divergence and an optional
+// colour correction after the inverse row pass
+static gfc_status solve_forward(gfc_plan_t p, const float* gx, const float* gy, const float* C,
+                                int edit, float tau2, float alpha, const float* I_mean,
+                                const float* I_std, float* u, int B, void* workspace,
+                                size_t ws_bytes, void* stream) {
   const WsLayout w = ws_layout(p, B);
   if (ws_bytes < w.total) return GFC_E_WORKSPACE;
   auto* ws = static_cast<unsigned char*>(workspace);
@@ -382,17 +381,51 @@ gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
   double* partial = reinterpret_cast<double*>(ws + w.red);
   double* mom = reinterpret_cast<double*>(ws + w.mom);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  gfc_status st = hip_status(p->rk->fwd(row_fwd_args(p, gx, gy, T, SB), B, s));
+  RowFwdArgs f = row_fwd_args(p, gx, gy, T, SB);
+  f.edit = edit;
+  f.C = C;
+  f.tau2 = tau2;
+  f.alpha = alpha;
+  gfc_status st = hip_status(p->rk->fwd(f, B, s));
   if (st != GFC_OK) return st;
   st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s, p->side, p->ev_fork,
                                  p->ev_join));
   if (st != GFC_OK) return st;
   RowInvArgs v = row_inv_args(p, T, u, partial);
-  v.mom = mom;
+  const bool color = I_mean != nullptr;
+  v.mom = color ? mom : nullptr;
   st = hip_status(p->rk->inv(v, B, s));
-  if (st != GFC_OK) return st;
+  if (st != GFC_OK || !color) return st;
   return hip_status(launch_color_apply(u, mom, inv_groups(p), I_mean, I_std,
                                        (long long)p->H * p->W, B, s));
+}
+
+gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
+                                 const float* I_mean, const float* I_std, float* u, int B,
+                                 void* workspace, size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!workspace || !gx || !gy || !u || !I_mean || !I_std) return GFC_E_ARG;
+  return solve_forward(p, gx, gy, nullptr, kEditNone, 0.f, 0.f, I_mean, I_std, u, B, workspace,
+                       ws_bytes, stream);
+}
+
+gfc_status gfc_solve_edit(gfc_plan_t p, const float* gx, const float* gy, const float* C,
+                          int mode, float param, const float* I_mean, const float* I_std,
+                          float* u, int B, void* workspace, size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (mode != GFC_EDIT_THRESHOLD && mode != GFC_EDIT_GDM) return GFC_E_ARG;
+  if (mode == GFC_EDIT_THRESHOLD && !(param >= 0.f)) return GFC_E_ARG;
+  if (mode == GFC_EDIT_GDM && !(param >= 0.f && param <= 1.f)) return GFC_E_ARG;
+  if ((I_mean == nullptr) != (I_std == nullptr)) return GFC_E_ARG;
+  if (B == 0) return GFC_OK;
+  if (!workspace || !gx || !gy || !u || (mode == GFC_EDIT_GDM && !C)) return GFC_E_ARG;
+  const float tau2 = mode == GFC_EDIT_THRESHOLD ? param * param : 0.f;  // rounded once
+  const float alpha = mode == GFC_EDIT_GDM ? param : 0.f;
+  return solve_forward(p, gx, gy, C, mode == GFC_EDIT_THRESHOLD ? kEditThreshold : kEditGdm,
+                       tau2, alpha, I_mean, I_std, u, B, workspace, ws_bytes, stream);
 }
 
 gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, float* dgx,

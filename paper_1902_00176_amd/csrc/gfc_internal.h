@@ -15,9 +15,17 @@ struct f2 {
 // SB[y, l] = Ey^[y, l] for l <= K (T1[y, 0] = 0). L is formed in float32 from the gradient
 // and two rows of L share one complex FFT; the K + 1 lowest bins of Ex and Ey are direct sums.
 constexpr int kLowBins = 4;  // K: row frequencies l <= K arrive at the column pass split
+// On-device gradient edits applied to every loaded pixel before the divergence:
+// threshold (Sec. 3.2.3): E kept where fl(fl(gx^2) + fl(gy^2)) >= tau2, else 0;
+// GDM (eq. (26)): E scaled to |E|^(1-alpha) C^alpha, orientation kept, 0 where E = 0.
+enum { kEditNone = 0, kEditThreshold = 1, kEditGdm = 2 };
 struct RowFwdArgs {
   const float* gx;
   const float* gy;
+  const float* C;     // [B][H][W] edge intensity (GDM only)
+  int edit;           // kEdit*
+  float tau2;         // threshold: tau^2 rounded to float32
+  float alpha;        // GDM weight in [0, 1]
   f2* T1;             // [B][H+1][NHP]  (NHP = NH rounded up to 32: row stride)
   f2* SB;             // [B][H][KP]     (KP = side-array row stride >= K + 1)
   const f2* twA;      // [N1][N2]: w_N^(k1 j), forward sign

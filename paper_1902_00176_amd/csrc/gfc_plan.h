@@ -80,6 +80,10 @@ inline RowFwdArgs row_fwd_args(const gfc_plan_s* p, const float* gx, const float
   RowFwdArgs a{};
   a.gx = gx;
   a.gy = gy;
+  a.C = nullptr;
+  a.edit = kEditNone;
+  a.tau2 = 0.f;
+  a.alpha = 0.f;
   a.T1 = T;
   a.SB = SB;
   a.twA = p->twA;

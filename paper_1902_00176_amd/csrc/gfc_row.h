@@ -228,19 +228,106 @@ __device__ __forceinline__ void pair_block(cx (&a)[N1], cx (&ax0)[kLowBins],
   low_acc<N1, Y1>(ax1, ay1, gx1, gy1, std::make_integer_sequence<int, kLowBins>{});
 }
 
-// blocks y1 < NB carry the support [0, W]; the rest of a[] is zero
-template <int N1, int N2, int NB, int Y1, class Rows>
-__device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
-                                          cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
-                                          cx (&ay1)[kLowBins + 1], const Rows& r, int W) {
-  if constexpr (Y1 < N1) {
-    if constexpr (Y1 < NB) pair_block<N1, N2, Y1>(a, ax0, ay0, ax1, ay1, r, W);
-    else a[Y1] = {0.f, 0.f};
-    pair_load<N1, N2, NB, Y1 + 1>(a, ax0, ay0, ax1, ay1, r, W);
+// Gradient edits of one pixel (before the divergence). Threshold: the decision uses the
+// same float32 rounding sequence as its specification (no contraction). GDM: the weighted
+// geometric mean of eq. (26) through log2/exp2 in float32.
+template <int EDIT>
+__device__ __forceinline__ void edit_pixel(float& gx, float& gy, float c, float tau2,
+                                           float alpha) {
+  if constexpr (EDIT == kEditThreshold) {
+    const float m = __fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy));
+    if (!(m >= tau2)) gx = gy = 0.f;
+  } else if constexpr (EDIT == kEditGdm) {
+    const float m = gx * gx + gy * gy;
+    const float lc = alpha > 0.f ? alpha * log2f(c) : 0.f;  // C^alpha, with C^0 = 1
+    const float sc = m > 0.f ? exp2f(lc - 0.5f * alpha * log2f(m)) : 0.f;
+    gx *= sc;
+    gy *= sc;
   }
 }
 
-template <int N1, int N2, int SLOTS, int NB>
+// Edited variant of one y1 block: both components (and C) at the five pixels the divergence
+// of a row pair touches, (y0, x), (y0, x-1), (y0+1, x), (y0+1, x-1), (y0-1, x), each edited
+// once. Uniform rows (one slot per wavefront): one descriptor per (field, row).
+struct EditRowsU {
+  rsrc_t x[3], y[3], c[3];  // rows y0 - 1, y0, y0 + 1
+  int vb;
+};
+template <int N1, int N2, int Y1, int EDIT>
+__device__ __forceinline__ void pair_block_edit(cx (&a)[N1], cx (&ax0)[kLowBins],
+                                                cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
+                                                cx (&ay1)[kLowBins + 1], const EditRowsU& r,
+                                                int W, float tau2, float alpha) {
+  const int v = r.vb + N2 * Y1 * 4;
+  auto px = [&](int row, int off, float& ex, float& ey) {
+    ex = bld1(r.x[row], off, 0);
+    ey = bld1(r.y[row], off, 0);
+    const float c = EDIT == kEditGdm ? bld1(r.c[row], off, 0) : 0.f;
+    edit_pixel<EDIT>(ex, ey, c, tau2, alpha);
+  };
+  float x0, y0, x0m, y0m, x1, y1, x1m, y1m, xm, ym;
+  px(1, v, x0, y0);
+  px(1, v - 4, x0m, y0m);
+  px(2, v, x1, y1);
+  px(2, v - 4, x1m, y1m);
+  px(0, v, xm, ym);
+  a[Y1] = {(x0 - x0m) + (y0 - ym), (x1 - x1m) + (y1 - y0)};
+  low_acc<N1, Y1>(ax0, ay0, x0, y0, std::make_integer_sequence<int, kLowBins>{});
+  low_acc<N1, Y1>(ax1, ay1, x1, y1, std::make_integer_sequence<int, kLowBins>{});
+}
+
+// Several slots per wavefront: per-lane row offsets into image-wide descriptors.
+struct EditRowsL {
+  rsrc_t gx, gy, c;
+  int z[3];       // byte offsets of (row, lane) for rows y0 - 1, y0, y0 + 1 (kOOB outside)
+  int zm0, zm1;   // x - 1 at y1 = 0 for rows y0, y0 + 1: kOOB for lane 0
+  int lane;
+};
+template <int N1, int N2, int Y1, int EDIT>
+__device__ __forceinline__ void pair_block_edit(cx (&a)[N1], cx (&ax0)[kLowBins],
+                                                cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
+                                                cx (&ay1)[kLowBins + 1], const EditRowsL& r,
+                                                int W, float tau2, float alpha) {
+  const int lim = W - N2 * Y1;
+  const bool xin = r.lane < lim, xmin = r.lane <= lim;
+  constexpr int so = N2 * Y1 * 4, som = Y1 == 0 ? 0 : N2 * Y1 * 4 - 4;
+  auto px = [&](int off, int soff, float& ex, float& ey) {
+    ex = bld1(r.gx, off, soff);
+    ey = bld1(r.gy, off, soff);
+    const float c = EDIT == kEditGdm ? bld1(r.c, off, soff) : 0.f;
+    edit_pixel<EDIT>(ex, ey, c, tau2, alpha);
+  };
+  float x0, y0, x0m, y0m, x1, y1, x1m, y1m, xm, ym;
+  px(xin ? r.z[1] : kOOB, so, x0, y0);
+  px(xmin ? (Y1 == 0 ? r.zm0 : r.z[1]) : kOOB, som, x0m, y0m);
+  px(xin ? r.z[2] : kOOB, so, x1, y1);
+  px(xmin ? (Y1 == 0 ? r.zm1 : r.z[2]) : kOOB, som, x1m, y1m);
+  px(xin ? r.z[0] : kOOB, so, xm, ym);
+  a[Y1] = {(x0 - x0m) + (y0 - ym), (x1 - x1m) + (y1 - y0)};
+  low_acc<N1, Y1>(ax0, ay0, x0, y0, std::make_integer_sequence<int, kLowBins>{});
+  low_acc<N1, Y1>(ax1, ay1, x1, y1, std::make_integer_sequence<int, kLowBins>{});
+}
+
+// blocks y1 < NB carry the support [0, W]; the rest of a[] is zero
+template <int N1, int N2, int NB, int Y1, int EDIT = kEditNone, class Rows>
+__device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
+                                          cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
+                                          cx (&ay1)[kLowBins + 1], const Rows& r, int W,
+                                          float tau2 = 0.f, float alpha = 0.f) {
+  if constexpr (Y1 < N1) {
+    if constexpr (Y1 < NB) {
+      if constexpr (EDIT == kEditNone)
+        pair_block<N1, N2, Y1>(a, ax0, ay0, ax1, ay1, r, W);
+      else
+        pair_block_edit<N1, N2, Y1, EDIT>(a, ax0, ay0, ax1, ay1, r, W, tau2, alpha);
+    } else {
+      a[Y1] = {0.f, 0.f};
+    }
+    pair_load<N1, N2, NB, Y1 + 1, EDIT>(a, ax0, ay0, ax1, ay1, r, W, tau2, alpha);
+  }
+}
+
+template <int N1, int N2, int SLOTS, int NB, int EDIT = kEditNone>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) {
   using C = RowCfg<N1, N2>;
   constexpr int KL = kLowBins;
@@ -273,19 +360,32 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     for (int l = 0; l < KL; ++l) ax0[l] = ax1[l] = {0.f, 0.f};
 #pragma unroll
     for (int l = 0; l <= KL; ++l) ay0[l] = ay1[l] = {0.f, 0.f};
-    if constexpr (SLOTS == 1) {
-      auto row = [&](const float* img, int y) {
-        const bool in = ok && y >= 0 && y < p.H;
-        return make_buf(img + (in ? (long long)y * p.W : 0), in ? (long long)p.W * 4 : 0);
-      };
+    auto row = [&](const float* img, int y) {
+      const bool in = ok && y >= 0 && y < p.H;
+      return make_buf(img + (in ? (long long)y * p.W : 0), in ? (long long)p.W * 4 : 0);
+    };
+    auto off = [&](int y) {
+      return (ok && lane < N2 && y >= 0 && y < p.H) ? (y * p.W + lane) * 4 : kOOB;
+    };
+    if constexpr (EDIT != kEditNone && SLOTS == 1) {
+      const float* ci = EDIT == kEditGdm ? p.C + b * p.img_in : gxi;
+      const EditRowsU rows{{row(gxi, y0 - 1), row(gxi, y0), row(gxi, y0 + 1)},
+                           {row(gyi, y0 - 1), row(gyi, y0), row(gyi, y0 + 1)},
+                           {row(ci, y0 - 1), row(ci, y0), row(ci, y0 + 1)},
+                           (lane < N2 ? lane * 4 : kOOB) + tz};
+      pair_load<N1, N2, NB, 0, EDIT>(a, ax0, ay0, ax1, ay1, rows, p.W, p.tau2, p.alpha);
+    } else if constexpr (EDIT != kEditNone) {
+      const float* ci = EDIT == kEditGdm ? p.C + b * p.img_in : gxi;
+      const int z0 = off(y0), z1 = off(y0 + 1);
+      const EditRowsL rows{rgx, rgy, make_buf(ci, p.img_in * 4), {off(y0 - 1), z0, z1},
+                           lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
+      pair_load<N1, N2, NB, 0, EDIT>(a, ax0, ay0, ax1, ay1, rows, p.W + tz, p.tau2, p.alpha);
+    } else if constexpr (SLOTS == 1) {
       // tz: the per-y1 offsets are formed in the loop, not hoisted and held live
       const PairRowsU rows{row(gxi, y0), row(gxi, y0 + 1), row(gyi, y0 - 1), row(gyi, y0),
                            row(gyi, y0 + 1), (lane < N2 ? lane * 4 : kOOB) + tz};
       pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W);
     } else {
-      auto off = [&](int y) {
-        return (ok && lane < N2 && y >= 0 && y < p.H) ? (y * p.W + lane) * 4 : kOOB;
-      };
       const int z0 = off(y0), z1 = off(y0 + 1);
       const PairRowsL rows{rgx, rgy, off(y0 - 1), z0, z1,
                            lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
@@ -365,12 +465,12 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
 }
 
 // NB: y1 blocks that can hold the support [0, W] (all N1, or N1/2 + 1 when 2 W <= N)
-template <int N1, int N2, int SLOTS, int NB>
+template <int N1, int N2, int SLOTS, int NB, int EDIT>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_fwd(RowFwdArgs p) {
   int bx, by;
   xcd_contiguous(bx, by);
-  row_fwd_body<N1, N2, SLOTS, NB>(p, bx, by);
+  row_fwd_body<N1, N2, SLOTS, NB, EDIT>(p, bx, by);
 }
 
 // ragged batches: one work item (image, block) per workgroup; pointers rebased per image
@@ -665,10 +765,21 @@ struct RowLaunch {
   static hipError_t fwd(const RowFwdArgs& a, int B, hipStream_t s) {
     const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
-    if (2 * a.W <= N1 * N2)
-      hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF>), grid, dim3(SLOTS * C::G), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1>), grid, dim3(SLOTS * C::G), 0, s, a);
+    const bool half = 2 * a.W <= N1 * N2;
+    const dim3 blk(SLOTS * C::G);
+    switch (a.edit) {
+      case kEditThreshold:
+        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditThreshold>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditThreshold>), grid, blk, 0, s, a);
+        break;
+      case kEditGdm:
+        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditGdm>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditGdm>), grid, blk, 0, s, a);
+        break;
+      default:
+        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditNone>), grid, blk, 0, s, a);
+    }
     return hipGetLastError();
   }
   static hipError_t inv(const RowInvArgs& a, int B, hipStream_t s) {

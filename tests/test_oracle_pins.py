@@ -404,3 +404,47 @@ def test_color_correction_is_invariant_to_positive_affine_maps():
 def test_color_correction_of_a_constant_image_is_the_source_mean():
     out = O.color_correct(np.full((1, 4, 5), 3.0), [0.7], [0.2])
     assert np.all(out == 0.7)
+
+
+# ---------------------------------------------------------------- gradient edits (Sec. 3.2.3, eq. (26))
+
+def test_threshold_edit_keeps_strong_and_drops_weak_gradients():
+    rng = np.random.default_rng(2701)
+    gx = rng.normal(size=(40, 50)).astype(np.float32)
+    gy = rng.normal(size=(40, 50)).astype(np.float32)
+    mag = np.hypot(gx.astype(np.float64), gy.astype(np.float64))
+    ex, ey = O.threshold_edit(gx, gy, 0.0)  # tau = 0 keeps every pixel
+    assert np.array_equal(ex, gx) and np.array_equal(ey, gy)
+    ex, ey = O.threshold_edit(gx, gy, 2 * mag.max())  # above every magnitude: all removed
+    assert not ex.any() and not ey.any()
+    tau = float(np.median(mag))
+    ex, ey = O.threshold_edit(gx, gy, tau)
+    kept = (ex != 0) | (ey != 0)
+    assert 0.3 < kept.mean() < 0.7
+    assert np.all(mag[kept] >= tau * (1 - 1e-6)) and np.all(mag[~kept] < tau * (1 + 1e-6))
+    assert np.array_equal(ex[kept], gx[kept]) and np.array_equal(ey[kept], gy[kept])
+    # a magnitude exactly at the level is kept: 3-4-5 with tau = 5
+    ex, ey = O.threshold_edit(np.float32([[3.0]]), np.float32([[4.0]]), 5.0)
+    assert ex[0, 0] == 3.0 and ey[0, 0] == 4.0
+
+
+def test_gdm_edit_special_cases_and_geometric_mean():
+    """Eq. (26): orientation of E, magnitude |E|^(1-alpha) C^alpha."""
+    rng = np.random.default_rng(2702)
+    gx = rng.normal(size=(30, 20))
+    gy = rng.normal(size=(30, 20))
+    C = rng.uniform(0.0, 2.0, size=(30, 20))
+    mag = np.hypot(gx, gy)
+    ex, ey = O.gdm_edit(gx, gy, C, 0.0)  # alpha = 0: the gradient alone
+    assert np.allclose(ex, gx, rtol=1e-14, atol=0) and np.allclose(ey, gy, rtol=1e-14, atol=0)
+    ex, ey = O.gdm_edit(gx, gy, C, 1.0)  # alpha = 1: the edge map's magnitude, E's direction
+    assert np.allclose(np.hypot(ex, ey), C, rtol=1e-13, atol=1e-15)
+    assert np.allclose(ex * gy - ey * gx, 0.0, atol=1e-13) and np.all(ex * gx + ey * gy >= 0)
+    ex, ey = O.gdm_edit(gx, gy, mag, 0.37)  # C = |E|: unchanged for any alpha
+    assert np.allclose(ex, gx, rtol=1e-13) and np.allclose(ey, gy, rtol=1e-13)
+    # log |E_p| is affine in alpha (a weighted geometric mean)
+    logs = [np.log(np.hypot(*O.gdm_edit(gx, gy, C + 0.1, a))) for a in (0.2, 0.5, 0.8)]
+    assert np.allclose(logs[1] - logs[0], logs[2] - logs[1], atol=1e-12)
+    # zero gradient: no orientation, E_p = 0
+    ex, ey = O.gdm_edit(np.zeros((2, 2)), np.zeros((2, 2)), np.ones((2, 2)), 0.5)
+    assert not ex.any() and not ey.any()
