@@ -175,6 +175,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-color", action="store_true")
+    ap.add_argument("--no-edit", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -318,6 +319,39 @@ def main():
         result["color"] = {"solves_per_s": B / (ms_c / 1e3), "ms_per_step": ms_c,
                            "over_plain": ms_c / ms_step,
                            "statistics": "source mean 0.5 and std 0.2 for every image"}
+
+    if not args.no_edit:
+        # gradient edits fused into the row pass (Sec. 3.2.3 thresholding, eq. (26) merging)
+        C = torch.rand_like(gx)
+        mag = torch.sqrt(gx[:4] * gx[:4] + gy[:4] * gy[:4])
+        tau = float(torch.quantile(mag.flatten()[::97], 0.5))
+
+        def edit_step(mode, param, cp):
+            st = L.gfc_solve_edit(hp, gx.data_ptr(), gy.data_ptr(), cp, mode,
+                                  __import__("ctypes").c_float(param), None, None, u.data_ptr(),
+                                  B, ws.data_ptr(), ws.numel(), sp)
+            if st != 0:
+                raise gfc.GFCError(st, "gfc_solve_edit")
+
+        edits = {}
+        for name, mode, param, cp in (("threshold", gfc.EDIT_THRESHOLD, tau, None),
+                                      ("gdm", gfc.EDIT_GDM, 0.5, C.data_ptr())):
+            for _ in range(args.warmup):
+                edit_step(mode, param, cp)
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            c0.record(stream)
+            for _ in range(args.steps):
+                edit_step(mode, param, cp)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            ms_e = c0.elapsed_time(c1) / args.steps
+            edits[name] = {"solves_per_s": B / (ms_e / 1e3), "ms_per_step": ms_e,
+                           "over_plain": ms_e / ms_step}
+        edits["params"] = f"threshold at the median gradient magnitude; gdm alpha 0.5, C ~ U[0,1]"
+        result["edit"] = edits
+        del C
 
     if not args.no_bwd:
         du = torch.randn_like(gx) * 0.1

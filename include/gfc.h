@@ -80,7 +80,8 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream);
  *   "row_fppw"  1..64   pairs of divergence rows handled by one FFT slot, forward row pass
  *   "row_ppw"   1..64   row pairs handled by one FFT slot in the pair-ordered row passes
  *   "col_c"     1..64   (power of two) columns per workgroup in the column pass
- *   "col_rows"  16|32   rows per thread in the column pass
+ *   "col_rows"  16|32   rows per thread in the forward column pass
+ *   "col_rows_b" 16|32  rows per thread in the backward column pass
  * The project's autotuner chooses these per (H, W, M, N); host-only.
  * gfc_plan_get_param also reads two fixed values: "low_bins" (K: row frequencies l <= K
  * reach the forward column pass as the x- and y-parts of the divergence separately) and

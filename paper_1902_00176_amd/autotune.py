@@ -8,7 +8,8 @@ tuning.json, which Plan() reads. Parameters only change speed, never results:
   row_fppw   pairs of divergence rows per FFT slot in the forward row pass
   row_ppw    row pairs per FFT slot in the pair-ordered passes  (row inverse, row backward-1)
   col_c      columns per workgroup in the column pass
-  col_rows   most rows per thread in the column pass (16 | 32)
+  col_rows   most rows per thread in the forward column pass (16 | 32)
+  col_rows_b most rows per thread in the backward column pass (16 | 32)
 
     python -m paper_1902_00176_amd.autotune --size 801 1200 1620 2400 100 [--write]
     python -m paper_1902_00176_amd.autotune --workloads [--write]
@@ -28,7 +29,7 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import paper_1902_00176_amd as gfc  # noqa: E402
 
-DEFAULT = {"row_fppw": 1, "row_ppw": 1, "col_c": 16, "col_rows": 16}
+DEFAULT = {"row_fppw": 1, "row_ppw": 1, "col_c": 16, "col_rows": 16, "col_rows_b": 16}
 GRID = {
     "row_fppw": [1, 2, 4],
     "row_ppw": [1, 2, 4],
@@ -107,12 +108,18 @@ def tune_size(H, W, M, N, B, torch, verbose=True):
     best["row_ppw"] = min(res)[1]
     # column pass
     res = []
+    # columns per workgroup (shared) and rows per thread (forward and backward separately)
     for c, r in GRID["col"]:
-        t = run({**DEFAULT, "col_c": c, "col_rows": r})
-        res.append((t["fwd2"] + t["bwd2"], (c, r), t))
+        t = run({**DEFAULT, "col_c": c, "col_rows": r, "col_rows_b": r})
+        res.append((c, r, t))
         log.append({"col_c": c, "col_rows": r, **t})
-    c, r = min(res)[1]
-    best["col_c"], best["col_rows"] = c, r
+    best_fb = None
+    for c in sorted({c for c, _, _ in res}):
+        f = min((t["fwd2"], r) for cc, r, t in res if cc == c)
+        b = min((t["bwd2"], r) for cc, r, t in res if cc == c)
+        if best_fb is None or f[0] + b[0] < best_fb[0]:
+            best_fb = (f[0] + b[0], c, f[1], b[1])
+    _, best["col_c"], best["col_rows"], best["col_rows_b"] = best_fb
     final = run(best)
     if verbose:
         for e in log:

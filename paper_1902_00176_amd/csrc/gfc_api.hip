@@ -121,7 +121,7 @@ void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
 // launch geometry that follows from the sizes and the tunable parameters
 void derive_geometry(gfc_plan_s* p) {
   p->gf = col_geometry(p->H + 1, p->M, p->r0, p->col_rows, p->col_c);
-  p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows, p->col_c);
+  p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows_b, p->col_c);
   p->nfslots = ((p->H + 2) / 2 + p->row_fppw - 1) / p->row_fppw;
   p->npairs = (p->H + 1) / 2;
   p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
@@ -215,6 +215,9 @@ gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
   } else if (!std::strcmp(name, "col_rows")) {
     if (value != 16 && value != 32) return GFC_E_ARG;
     p->col_rows = value;
+  } else if (!std::strcmp(name, "col_rows_b")) {
+    if (value != 16 && value != 32) return GFC_E_ARG;
+    p->col_rows_b = value;
   } else {
     return GFC_E_ARG;
   }
@@ -228,6 +231,7 @@ gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
   else if (!std::strcmp(name, "row_ppw")) *value = p->row_ppw;
   else if (!std::strcmp(name, "col_c")) *value = p->gf.C;
   else if (!std::strcmp(name, "col_rows")) *value = p->col_rows;
+  else if (!std::strcmp(name, "col_rows_b")) *value = p->col_rows_b;
   else if (!std::strcmp(name, "low_bins")) *value = p->K;
   else if (!std::strcmp(name, "low_bins_b")) *value = p->Kb;
   else return GFC_E_ARG;
@@ -484,6 +488,7 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     c.Rp = p->gb.Rp;
     c.img_t = img_t;
     c.img_sd = img_sd;
+    c.nimg = B;
     const gfc_status st = hip_status(launch_col_bwd(c, B, s));
     if (st != GFC_OK) return st;
   }

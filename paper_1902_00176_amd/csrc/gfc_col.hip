@@ -500,7 +500,20 @@ __global__ void __launch_bounds__(kColMaxThreads) k_col_bwd(ColBwdArgs p) {
   dc* E = s_mem;
   dc* U = s_mem + p.nseg * p.C;
   double* s_misc = reinterpret_cast<double*>(s_mem + 2 * p.nseg * p.C);
-  col_bwd_tile<LMAX, TAIL>(p, blockIdx.x, blockIdx.y, E, U, s_misc);
+  // tiles holding columns l <= Kb (long carry sums) are dispatched first, for every image
+  const int ntiles = (p.NH + p.C - 1) / p.C;
+  const int nlow = min(ntiles, (p.Kb + p.C) / p.C);
+  const int i = blockIdx.x;
+  int tile, b;
+  if (i < nlow * p.nimg) {
+    tile = i % nlow;
+    b = i / nlow;
+  } else {
+    const int j = i - nlow * p.nimg, nr = ntiles - nlow;
+    tile = nlow + j % nr;
+    b = j / nr;
+  }
+  col_bwd_tile<LMAX, TAIL>(p, tile, b, E, U, s_misc);
 }
 
 namespace {
@@ -589,7 +602,9 @@ hipError_t launch_col_fwd_rg(const RgBase& base, const RgCol* tab, const RgItem*
 
 hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s) {
   const size_t shm = size_t(2 * a.nseg * a.C) * sizeof(dc) + 8 * sizeof(double);
-  const dim3 grid((a.NH + a.C - 1) / a.C, B), blk(col_block(a.C, a.nseg));
+  // one-dimensional grid: k_col_bwd maps its index to (tile, image), low tiles first
+  const dim3 grid(((a.NH + a.C - 1) / a.C) * B), blk(col_block(a.C, a.nseg));
+  if (a.nimg != B) return hipErrorInvalidValue;
   const bool tail = a.Rp != a.nseg * a.Lseg;
   if (a.Lseg == 16) {
     if (tail) hipLaunchKernelGGL((k_col_bwd<16, true>), grid, blk, shm, s, a);

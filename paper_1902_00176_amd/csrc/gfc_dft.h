@@ -1,8 +1,10 @@
 // gfc_dft.h - register-resident mixed-radix DFTs (radix 2, 3, 4, 5) for gfx950.
 //
-// A length-n DFT of a thread-private array is expanded at compile time by decimation in
-// time: n = R * Q, R sub-DFTs of length Q over the decimated inputs, a twiddle by
-// w_n^(r k'), then Q DFTs of length R. Every index is a compile-time constant after
+// A length-n DFT of a thread-private array is expanded at compile time. Lengths with two
+// coprime factors n = A * B use the prime-factor (Good-Thomas) index maps, which need no
+// twiddles between the factors (DftSel). Prime powers use decimation in time: n = R * Q, R
+// sub-DFTs of length Q over the decimated inputs, a twiddle by w_n^(r k'), then Q DFTs of
+// length R. Every index is a compile-time constant after
 // unrolling, so the arrays live in VGPRs and every twiddle is an immediate. Twiddle
 // constants are evaluated in float64 (constexpr series after exact octant reduction) and
 // rounded once to float32. Multiplications by 1, -1, +-i and (+-1 +-i)/sqrt(2) are
@@ -110,6 +112,30 @@ constexpr int dft_radix(int n) {
          : (n % 5 == 0 && n > 5) ? 5 : n;
 }
 
+// Coprime split n = A * B for the prime-factor (Good-Thomas) algorithm: A = the power of two
+// in n, else the power of three; 1 when n is a prime power (then Cooley-Tukey is used).
+constexpr int pow_part(int n, int p) {
+  int a = 1;
+  while (n % p == 0) {
+    n /= p;
+    a *= p;
+  }
+  return a;
+}
+constexpr int pfa_split(int n) {
+  const int a2 = pow_part(n, 2);
+  if (a2 > 1 && a2 < n) return a2;
+  const int a3 = pow_part(n, 3);
+  if (a3 > 1 && a3 < n) return a3;
+  return 1;
+}
+// multiplicative inverse of a modulo m (a, m coprime), by search: compile time only
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
 template <int N, int SIGN>
 struct Dft;
 
@@ -182,6 +208,39 @@ struct Dft<5, SIGN> {
   }
 };
 
+// Prime-factor algorithm for coprime N = A * B (no twiddles between the factors):
+// input index n = (B n1 + A n2) mod N, output index k = (eA k1 + eB k2) mod N with
+// eA = B (B^-1 mod A) (1 mod A, 0 mod B) and eB = A (A^-1 mod B) (0 mod A, 1 mod B); a
+// length-A DFT over n1 for each n2, then a length-B DFT over n2 for each k1.
+template <int N, int SIGN, int A = pfa_split(N)>
+struct DftSel;
+
+template <int N, int SIGN>
+struct DftPfa {
+  static constexpr int A = pfa_split(N);
+  static constexpr int B = N / A;
+  static constexpr int eA = (B * inv_mod(B % A, A)) % N;
+  static constexpr int eB = (A * inv_mod(A % B, B)) % N;
+  __host__ __device__ __forceinline__ static void run(cx (&a)[N]) {
+    cx t[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n2][n1] = a[(B * n1 + A * n2) % N];
+      DftSel<A, SIGN>::run(t[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      cx c[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) c[n2] = t[n2][k1];
+      DftSel<B, SIGN>::run(c);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) a[(eA * k1 + eB * k2) % N] = c[k2];
+    }
+  }
+};
+
 template <int N, int SIGN>
 struct Dft {
   static constexpr int R = dft_radix(N);
@@ -216,6 +275,16 @@ struct Dft {
 #pragma unroll
     for (int r = 0; r < R; ++r) Dft<Q, SIGN>::run(sub[r]);
     combine<0>(a, sub);
+  }
+};
+
+// Dispatch: the prime-factor algorithm for lengths with a coprime split, Cooley-Tukey for
+// prime powers (and the small radices themselves).
+template <int N, int SIGN, int A>
+struct DftSel {
+  __host__ __device__ __forceinline__ static void run(cx (&a)[N]) {
+    if constexpr (A > 1) DftPfa<N, SIGN>::run(a);
+    else Dft<N, SIGN>::run(a);
   }
 };
 

@@ -142,6 +142,7 @@ struct ColBwdArgs {
   int H, M, NH, NHP, Kb, KbP, r0;
   int C, nseg, Lseg, Llast, Rp;   // R = H rows of input
   long long img_t, img_sd;
+  int nimg;           // images of the launch (B)
 };
 
 // ---- ragged batches ---------------------------------------------------------------------

@@ -14,7 +14,8 @@ namespace gfc {
 // Launch geometry defaults; each can be changed per plan with gfc_plan_set_param.
 constexpr int kFwdPairsPerSlot = 1;  // "row_fppw": pairs of L rows per slot, forward row pass
 constexpr int kColC = 16;         // "col_c": columns per workgroup in the column pass
-constexpr int kColRows = 16;      // "col_rows": rows per thread in the column pass (16|32)
+constexpr int kColRows = 16;      // "col_rows", "col_rows_b": rows per thread in the forward
+                                  // and the backward column pass (16|32)
 constexpr int kPairsPerSlot = 1;  // "row_ppw": row pairs per slot in the pair-ordered passes
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -31,7 +32,7 @@ struct gfc_plan_s {
   gfc::ColGeom gf{}, gb{};
   // launch geometry (gfc_plan_set_param) and what follows from it
   int row_fppw = gfc::kFwdPairsPerSlot, row_ppw = gfc::kPairsPerSlot, col_c = gfc::kColC,
-      col_rows = gfc::kColRows;
+      col_rows = gfc::kColRows, col_rows_b = gfc::kColRows;
   int nfslots = 0, npairs = 0;
   int ntiles_f = 0, ntiles_b = 0, nsums = 0;
   // device tables, one allocation (gfc_green_build)

@@ -78,7 +78,7 @@ __device__ __forceinline__ void fwd_fft_to_lds(cx (&a)[N1], float* re, float* im
                                                rsrc_t twA, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N2) {
-    Dft<N1, -1>::run(a);
+    DftSel<N1, -1>::run(a);
 #pragma unroll
     for (int k1 = 1; k1 < N1; ++k1) {
       const f2b w = bld2(twA, lane * 8, tz + k1 * N2 * 8);
@@ -95,7 +95,7 @@ __device__ __forceinline__ void fwd_fft_to_lds(cx (&a)[N1], float* re, float* im
   if (lane < N1) {
 #pragma unroll
     for (int j = 0; j < N2; ++j) b[j] = {re[lane * C::SA + j], im[lane * C::SA + j]};
-    Dft<N2, -1>::run(b);
+    DftSel<N2, -1>::run(b);
   }
   slot_sync();
   if (lane < N1) {
@@ -115,7 +115,7 @@ __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], floa
                                                   float* im, int lane, rsrc_t twB, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N1) {
-    Dft<N2, +1>::run(b);
+    DftSel<N2, +1>::run(b);
 #pragma unroll
     for (int j2 = 1; j2 < N2; ++j2) {
       const f2b w = bld2(twB, lane * 8, tz + j2 * N1 * 8);
@@ -131,7 +131,7 @@ __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], floa
   if (lane < N2) {
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) a[k1] = {re[lane * C::SB + k1], im[lane * C::SB + k1]};
-    Dft<N1, +1>::run(a);
+    DftSel<N1, +1>::run(a);
   }
 }
 

@@ -116,13 +116,14 @@ def test_ragged_create_host_logic():
 def test_plan_parameters_round_trip_and_fixed_low_bins():
     """Launch parameters are set and read back on the host; out-of-range values and unknown
     names are rejected; K and Kb are read-only values of the plan."""
-    p = gfc.Plan(801, 1200, params={"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32},
-                 tuned=False)
-    assert p.params == {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32}
+    want = {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32, "col_rows_b": 16}
+    p = gfc.Plan(801, 1200, params=want, tuned=False)
+    assert p.params == want
     assert p.get_param("low_bins") == 4
     assert p.get_param("low_bins_b") == 64
     L = gfc.lib()
     for name, value in (("row_fppw", 0), ("row_fppw", 65), ("col_c", 3), ("col_rows", 24),
+                        ("col_rows_b", 8),
                         ("low_bins", 8), ("row_strip", 4)):
         assert L.gfc_plan_set_param(p.handle, name.encode(), value) == 1, (name, value)
     # a short row: Kb is capped by the half spectrum
