@@ -119,6 +119,20 @@ gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
                                  void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Forward solve from the Laplacian itself, Algorithm B's literal input:
+ *   L : [B][H+1][W+1] float32, the divergence / Laplacian on the support of div E for H x W
+ *       forward-difference fields (rows 0..H, columns 0..W of the image block; the Laplacian
+ *       of an image whose first row and column are zero has exactly this support)
+ *   u : [B][H][W] as for gfc_solve_batch.
+ * L should sum to 0 (every divergence does): the torus solve cannot represent a net source,
+ * and the DC column of L is integrated along y from row 0. Precision: the split of the
+ * lowest row frequencies into x- and y-parts that protects gfc_solve_batch is not available
+ * for a given L; its row transform is a plain float32 FFT of L.
+ */
+gfc_status gfc_solve_laplacian(gfc_plan_t p, const float* L, float* u, int B, void* workspace,
+                               size_t ws_bytes, void* stream);
+
+/*
  * Gradient-domain editing in one call (Sec. 3.2): an edit of the gradient field, applied on
  * the device to each pixel as it is loaded, then the forward solve, then optionally the
  * colour correction of eq. (25).

@@ -40,7 +40,7 @@ __all__ = [
     "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_algorithm_a",
     "embed", "divergence", "solve_fft", "solve_direct", "lstsq_torus", "torus_gradient",
     "solve_backward", "green_function", "cpu_workers", "color_correct", "threshold_edit",
-    "gdm_edit",
+    "gdm_edit", "solve_laplacian",
 ]
 
 
@@ -272,3 +272,26 @@ def gdm_edit(gx, gy, C, alpha: float):
     safe = np.where(nz, mag, 1.0)
     scale = np.where(nz, safe ** (-alpha) * C ** alpha, 0.0)
     return gx * scale, gy * scale
+
+
+def solve_laplacian(L, M: int, N: int, workers: int | None = None) -> np.ndarray:
+    """Algorithm B with its literal input: the Laplacian itself rather than a gradient field.
+
+    L: [H+1, W+1] or [B, H+1, W+1], the support of the Laplacian of an H x W image whose
+    first row and column are zero (the paper pads before differentiating), i.e. the same
+    support as div E for H x W forward-difference fields. It is embedded at the block offset
+    (oy, ox) of the H x W image, v = R(F^-1(F(L) o G^)) (eq. (23)), u = v[block] - v[0,0].
+    The torus solve only sees L up to its mean (G^(0,0) = 0); L is expected to sum to 0, as
+    every divergence and every Laplacian of a zero-padded field does. Returns [.., H, W]."""
+    L, single = _as_batch(L)
+    B, H1, W1 = L.shape
+    H, W = H1 - 1, W1 - 1
+    oy, ox = block_offset(H, W, M, N)
+    Gh = green_spectrum(M, N)[:, : N // 2 + 1]
+    w = workers if workers is not None else cpu_workers()
+    out = np.empty((B, H, W), dtype=np.float64)
+    for b in range(B):
+        Lt = embed(L[b], M, N, oy, ox)
+        v = sfft.irfft2(sfft.rfft2(Lt, workers=w) * Gh, s=(M, N), workers=w)
+        out[b] = v[oy:oy + H, ox:ox + W] - v[0, 0]
+    return out[0] if single else out

@@ -60,6 +60,7 @@ def lib():
             L.gfc_solve_batch_color.argtypes = [vp, vp, vp, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_edit.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, vp, vp, vp, i, vp,
                                          sz, vp]
+            L.gfc_solve_laplacian.argtypes = [vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_batch_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_plan_set_param.argtypes = [vp, ctypes.c_char_p, i]
@@ -313,6 +314,29 @@ class Plan:
                 "gfc_solve_edit")
         return u
 
+    def solve_laplacian(self, L, out=None, workspace=None, stream=None):
+        """Solve from the Laplacian itself (Algorithm B): L [..., H+1, W+1] float32 on the
+        support of div E, summing to 0. Returns u [..., H, W]."""
+        import torch
+        dev = L.device
+        if dev.type != "cuda" or L.dtype != torch.float32:
+            raise TypeError("L must be a float32 CUDA tensor")
+        if tuple(L.shape[-2:]) != (self.H + 1, self.W + 1):
+            raise ValueError(f"expected [..., {self.H + 1}, {self.W + 1}], got {tuple(L.shape)}")
+        self.build(dev)
+        L = L.contiguous()
+        B = L.numel() // ((self.H + 1) * (self.W + 1))
+        u = out if out is not None else torch.empty(L.shape[:-2] + (self.H, self.W),
+                                                    dtype=torch.float32, device=dev)
+        ws = self._workspace(torch, dev, B, workspace)
+        with torch.cuda.device(dev):
+            _check(lib().gfc_solve_laplacian(self._h, L.data_ptr(), u.data_ptr(), B,
+                                             ws.data_ptr() if ws is not None else None,
+                                             ws.numel() if ws is not None else 0,
+                                             _stream_ptr(torch, dev, stream)),
+                   "gfc_solve_laplacian")
+        return u
+
     def backward(self, du, workspace=None, stream=None):
         torch, dev = self._prep(du)
         du = du.contiguous()
@@ -361,6 +385,11 @@ def solve_color(gx, gy, I_mean, I_std, M: int = 0, N: int = 0, **kw):
     """GFC(gx, gy) with the colour correction of eq. (25) to the source statistics."""
     return get_plan(gx.shape[-2], gx.shape[-1], M or 0, N or 0).solve_color(gx, gy, I_mean,
                                                                             I_std, **kw)
+
+
+def solve_laplacian(L, M: int = 0, N: int = 0, **kw):
+    """u from the Laplacian L [..., H+1, W+1] (Algorithm B's input)."""
+    return get_plan(L.shape[-2] - 1, L.shape[-1] - 1, M or 0, N or 0).solve_laplacian(L, **kw)
 
 
 EDIT_THRESHOLD = 1

@@ -392,6 +392,10 @@ static gfc_status solve_forward(gfc_plan_t p, const float* gx, const float* gy, 
   f.alpha = alpha;
   gfc_status st = hip_status(p->rk->fwd(f, B, s));
   if (st != GFC_OK) return st;
+  if (edit == kInLaplacian) {
+    st = hip_status(launch_sb_prefix(SB, p->H, p->KP, f.img_sb, B, s));
+    if (st != GFC_OK) return st;
+  }
   st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s, p->side, p->ev_fork,
                                  p->ev_join));
   if (st != GFC_OK) return st;
@@ -413,6 +417,17 @@ gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
   if (!workspace || !gx || !gy || !u || !I_mean || !I_std) return GFC_E_ARG;
   return solve_forward(p, gx, gy, nullptr, kEditNone, 0.f, 0.f, I_mean, I_std, u, B, workspace,
                        ws_bytes, stream);
+}
+
+gfc_status gfc_solve_laplacian(gfc_plan_t p, const float* L, float* u, int B, void* workspace,
+                               size_t ws_bytes, void* stream) {
+  if (!p || B < 0) return GFC_E_ARG;
+  if (!p->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!workspace || !L || !u) return GFC_E_ARG;
+  if ((long long)(p->H + 1) * (p->W + 1) * 4 >= (1LL << 30)) return GFC_E_SIZE;
+  return solve_forward(p, nullptr, nullptr, L, kInLaplacian, 0.f, 0.f, nullptr, nullptr, u, B,
+                       workspace, ws_bytes, stream);
 }
 
 gfc_status gfc_solve_edit(gfc_plan_t p, const float* gx, const float* gy, const float* C,

@@ -18,11 +18,12 @@ constexpr int kLowBins = 4;  // K: row frequencies l <= K arrive at the column p
 // On-device gradient edits applied to every loaded pixel before the divergence:
 // threshold (Sec. 3.2.3): E kept where fl(fl(gx^2) + fl(gy^2)) >= tau2, else 0;
 // GDM (eq. (26)): E scaled to |E|^(1-alpha) C^alpha, orientation kept, 0 where E = 0.
-enum { kEditNone = 0, kEditThreshold = 1, kEditGdm = 2 };
+// kInLaplacian: the input is the divergence itself, L [B][H+1][W+1] (Algorithm B's input).
+enum { kEditNone = 0, kEditThreshold = 1, kEditGdm = 2, kInLaplacian = 3 };
 struct RowFwdArgs {
   const float* gx;
   const float* gy;
-  const float* C;     // [B][H][W] edge intensity (GDM only)
+  const float* C;     // [B][H][W] edge intensity (GDM), or L [B][H+1][W+1] (kInLaplacian)
   int edit;           // kEdit*
   float tau2;         // threshold: tau^2 rounded to float32
   float alpha;        // GDM weight in [0, 1]
@@ -50,6 +51,10 @@ struct RowInvArgs {
   long long img_t2, img_u;
   double* mom;        // [B][gridDim.x][2]: sums of u and u^2 per workgroup, or null
 };
+
+// Laplacian input: SB[y][0] <- sum_{y' <= y} SB[y'][0] for y in [0, H) of every image, so the
+// column pass's split form (1 - S) b reproduces the DC column of L (float64 running sums).
+hipError_t launch_sb_prefix(f2* SB, int H, int KP, long long img_sb, int B, hipStream_t s);
 
 // Colour correction of eq. (25) in place on u [B][npix]: every workgroup of image b reduces
 // that image's nparts moment pairs in a fixed order, then u <- (u - mean) * I_std[b] / std + I_mean[b].

@@ -308,6 +308,36 @@ __device__ __forceinline__ void pair_block_edit(cx (&a)[N1], cx (&ax0)[kLowBins]
   low_acc<N1, Y1>(ax1, ay1, x1, y1, std::make_integer_sequence<int, kLowBins>{});
 }
 
+// Laplacian input: rows y0 and y0 + 1 of L [H+1][W+1] straight into the FFT input.
+struct LapRowsU {
+  rsrc_t r0, r1;  // one descriptor per row, range W + 1 elements (empty past row H)
+  int vb;
+};
+template <int N1, int N2, int Y1>
+__device__ __forceinline__ void lap_block(cx (&a)[N1], const LapRowsU& r, int W) {
+  const int v = r.vb + N2 * Y1 * 4;
+  a[Y1] = {bld1(r.r0, v, 0), bld1(r.r1, v, 0)};
+}
+struct LapRowsL {
+  rsrc_t img;
+  int z0, z1;  // byte offsets of (row, lane), kOOB past row H or for lanes j >= N2
+  int lane;
+};
+template <int N1, int N2, int Y1>
+__device__ __forceinline__ void lap_block(cx (&a)[N1], const LapRowsL& r, int W) {
+  const bool xin = r.lane <= W - N2 * Y1;  // x <= W
+  constexpr int so = N2 * Y1 * 4;
+  a[Y1] = {bld1(r.img, xin ? r.z0 : kOOB, so), bld1(r.img, xin ? r.z1 : kOOB, so)};
+}
+template <int N1, int N2, int NB, int Y1, class Rows>
+__device__ __forceinline__ void lap_load(cx (&a)[N1], const Rows& r, int W) {
+  if constexpr (Y1 < N1) {
+    if constexpr (Y1 < NB) lap_block<N1, N2, Y1>(a, r, W);
+    else a[Y1] = {0.f, 0.f};
+    lap_load<N1, N2, NB, Y1 + 1>(a, r, W);
+  }
+}
+
 // blocks y1 < NB carry the support [0, W]; the rest of a[] is zero
 template <int N1, int N2, int NB, int Y1, int EDIT = kEditNone, class Rows>
 __device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
@@ -367,7 +397,23 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     auto off = [&](int y) {
       return (ok && lane < N2 && y >= 0 && y < p.H) ? (y * p.W + lane) * 4 : kOOB;
     };
-    if constexpr (EDIT != kEditNone && SLOTS == 1) {
+    if constexpr (EDIT == kInLaplacian && SLOTS == 1) {
+      const float* li = p.C + b * (long long)(p.H + 1) * (p.W + 1);
+      auto lrow = [&](int y) {
+        const bool in = ok && y <= p.H;
+        return make_buf(li + (in ? (long long)y * (p.W + 1) : 0), in ? (long long)(p.W + 1) * 4 : 0);
+      };
+      const LapRowsU rows{lrow(y0), lrow(y0 + 1), (lane < N2 ? lane * 4 : kOOB) + tz};
+      lap_load<N1, N2, NB, 0>(a, rows, p.W);
+    } else if constexpr (EDIT == kInLaplacian) {
+      const float* li = p.C + b * (long long)(p.H + 1) * (p.W + 1);
+      auto loff = [&](int y) {
+        return (ok && lane < N2 && y <= p.H) ? (y * (p.W + 1) + lane) * 4 : kOOB;
+      };
+      const LapRowsL rows{make_buf(li, (long long)(p.H + 1) * (p.W + 1) * 4), loff(y0),
+                          loff(y0 + 1), lane};
+      lap_load<N1, N2, NB, 0>(a, rows, p.W + tz);
+    } else if constexpr (EDIT != kEditNone && SLOTS == 1) {
       const float* ci = EDIT == kEditGdm ? p.C + b * p.img_in : gxi;
       const EditRowsU rows{{row(gxi, y0 - 1), row(gxi, y0), row(gxi, y0 + 1)},
                            {row(gyi, y0 - 1), row(gyi, y0), row(gyi, y0 + 1)},
@@ -393,6 +439,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     }
 
     // lane factors w_N^(l j) (Ex also times 1 - w_N^l), then the sums over the lanes
+    constexpr int NVL = EDIT == kInLaplacian ? 0 : (NV + C::G - 1) / C::G;
+    float lowsum[NVL > 0 ? NVL : 1];
+    if constexpr (EDIT != kInLaplacian) {
 #pragma unroll
     for (int l = 0; l <= KL; ++l) {
       const f2b wy = bld2(rtl, lane * 8, tz + (KL + 1 + l) * C::G * 8);
@@ -416,8 +465,6 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     }
     slot_sync();
     // lane t sums values t, t + G, ... over the N2 lanes that hold elements
-    constexpr int NVL = (NV + C::G - 1) / C::G;
-    float lowsum[NVL];
 #pragma unroll
     for (int k = 0; k < NVL; ++k) {
       lowsum[k] = 0.f;
@@ -428,6 +475,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
       }
     }
     slot_sync();
+    }  // EDIT != kInLaplacian
 
     fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
 
@@ -437,7 +485,23 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
 #pragma unroll
     for (int i = 0; i < C::NI; ++i) {
       const int l = lane + C::G * i;
-      if (ok && l < C::NH && (l == 0 || l > KL)) {
+      if constexpr (EDIT == kInLaplacian) {
+        // every bin of L^ goes to T1; the split side array gets (0 for l > 0 and) the DC
+        // bin, turned into its running sum over the rows by launch_sb_prefix
+        if (ok && l < C::NH) {
+          const int m = (l == 0) ? 0 : C::N - l;
+          const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
+          const cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
+          const cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
+          bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
+          if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
+          if (l <= KL) {
+            const bool dc = l == 0;
+            if (y0 < p.H) bst2(rSB, dc ? A.x : 0.f, dc ? A.y : 0.f, (y0 * p.KP + l) * 8, 0);
+            if (y0 + 1 < p.H) bst2(rSB, dc ? B.x : 0.f, dc ? B.y : 0.f, ((y0 + 1) * p.KP + l) * 8, 0);
+          }
+        }
+      } else if (ok && l < C::NH && (l == 0 || l > KL)) {
         const int m = (l == 0) ? 0 : C::N - l;
         const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
         cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
@@ -775,6 +839,10 @@ struct RowLaunch {
       case kEditGdm:
         if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditGdm>), grid, blk, 0, s, a);
         else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditGdm>), grid, blk, 0, s, a);
+        break;
+      case kInLaplacian:
+        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kInLaplacian>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kInLaplacian>), grid, blk, 0, s, a);
         break;
       default:
         if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);

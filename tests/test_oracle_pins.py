@@ -448,3 +448,45 @@ def test_gdm_edit_special_cases_and_geometric_mean():
     # zero gradient: no orientation, E_p = 0
     ex, ey = O.gdm_edit(np.zeros((2, 2)), np.zeros((2, 2)), np.ones((2, 2)), 0.5)
     assert not ex.any() and not ey.any()
+
+
+# ---------------------------------------------------------------- Laplacian input (Algorithm B)
+
+def _support_divergence(gx, gy):
+    """div E on the (H+1) x (W+1) support, from the definition (backward differences)."""
+    H, W = gx.shape
+    Ex = np.zeros((H + 1, W + 1)); Ex[:H, :W] = gx
+    Ey = np.zeros((H + 1, W + 1)); Ey[:H, :W] = gy
+    Exl = np.zeros_like(Ex); Exl[:, 1:] = Ex[:, :-1]
+    Eyu = np.zeros_like(Ey); Eyu[1:, :] = Ey[:-1, :]
+    return (Ex - Exl) + (Ey - Eyu)
+
+
+def test_laplacian_input_equals_gradient_input():
+    """Solving div E directly is the gradient solve (eq. (3) then eq. (23))."""
+    rng = np.random.default_rng(3301)
+    for H, W, M, N in ((6, 7, 14, 16), (20, 31, 40, 64)):
+        gx, gy = _rand_field(rng, H, W)
+        L = _support_divergence(gx, gy)
+        assert abs(L.sum()) < 1e-12
+        ref = O.solve_fft(gx, gy, M, N)
+        assert np.max(np.abs(O.solve_laplacian(L, M, N) - ref)) < 1e-12 * max(1, np.abs(ref).max())
+
+
+def test_laplacian_of_a_framed_image_reconstructs_it():
+    """Algorithm B on the 5-point Laplacian (Algorithm A's stencil) of a zero-framed image
+    returns the image, offset included (the corner lies in the padding)."""
+    rng = np.random.default_rng(3302)
+    H, W, M, N = 20, 31, 40, 64
+    S, _, _ = _framed_conservative(rng, H, W)
+    P = np.zeros((H + 3, W + 3)); P[1:H + 1, 1:W + 1] = S  # S with a zero ring
+    Lfull = P[:-2, 1:-1] + P[2:, 1:-1] + P[1:-1, :-2] + P[1:-1, 2:] - 4 * P[1:-1, 1:-1]
+    L = Lfull[:H + 1, :W + 1]  # row -1 and column -1 are zero for a framed image
+    assert np.allclose(Lfull[H + 1:, :], 0) or Lfull.shape[0] == H + 1
+    u = O.solve_laplacian(L, M, N)
+    assert np.max(np.abs(u - S)) < 1e-12
+    # and Algorithm A's spectrum built from the printed kernels gives the same solve
+    Gh = O.green_spectrum_algorithm_a(M, N)
+    oy, ox = O.block_offset(H, W, M, N)
+    v = np.real(np.fft.ifft2(np.fft.fft2(O.embed(L, M, N, oy, ox)) * Gh))
+    assert np.max(np.abs((v[oy:oy + H, ox:ox + W] - v[0, 0]) - S)) < 1e-11
