@@ -40,7 +40,8 @@ __all__ = [
     "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_algorithm_a",
     "embed", "divergence", "solve_fft", "solve_direct", "lstsq_torus", "torus_gradient",
     "solve_backward", "green_function", "cpu_workers", "color_correct", "threshold_edit",
-    "gdm_edit", "solve_laplacian",
+    "gdm_edit", "solve_laplacian", "block_offset3", "green_spectrum3", "solve3_fft",
+    "lstsq_torus3",
 ]
 
 
@@ -295,3 +296,80 @@ def solve_laplacian(L, M: int, N: int, workers: int | None = None) -> np.ndarray
         v = sfft.irfft2(sfft.rfft2(Lt, workers=w) * Gh, s=(M, N), workers=w)
         out[b] = v[oy:oy + H, ox:ox + W] - v[0, 0]
     return out[0] if single else out
+
+
+# ---------------------------------------------------------------- n-D (three dimensions)
+# The method holds in any dimension (eq. (5) and Sec. 2): the Green's function of the
+# discrete Laplacian on a P x M x N torus has the spectrum 1 / lambda with
+#     lambda(kz, ky, kx) = -4 sin^2(pi kz/P) - 4 sin^2(pi ky/M) - 4 sin^2(pi kx/N),
+# the 7-point stencil's symbol, and the same readings apply: G^(0,0,0) = 0, the block is
+# centred, the constant is the value at the grid corner (0,0,0). Volumes are [D, H, W]
+# (z, y, x); the gradient is (gx, gy, gz) with forward differences and a zero exterior.
+
+def block_offset3(D: int, H: int, W: int, P: int, M: int, N: int):
+    if P < D + 2 or M < H + 2 or N < W + 2:
+        raise ValueError("torus must exceed the volume by at least 2 in each direction")
+    return (P - D) // 2, (M - H) // 2, (N - W) // 2
+
+
+def green_spectrum3(P: int, M: int, N: int) -> np.ndarray:
+    """1 / lambda on the P x M x N torus, 0 at the DC bin."""
+    lz = -4.0 * np.sin(np.pi * np.arange(P) / P) ** 2
+    ly = -4.0 * np.sin(np.pi * np.arange(M) / M) ** 2
+    lx = -4.0 * np.sin(np.pi * np.arange(N) / N) ** 2
+    lam = lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
+    G = np.zeros_like(lam)
+    nz = lam != 0
+    G[nz] = 1.0 / lam[nz]
+    return G
+
+
+def _divergence3(gx, gy, gz, P, M, N, o):
+    E = []
+    for g in (gx, gy, gz):
+        t = np.zeros((P, M, N))
+        D, H, W = g.shape
+        t[o[0]:o[0] + D, o[1]:o[1] + H, o[2]:o[2] + W] = g
+        E.append(t)
+    return ((E[0] - np.roll(E[0], 1, axis=2)) + (E[1] - np.roll(E[1], 1, axis=1))
+            + (E[2] - np.roll(E[2], 1, axis=0)))
+
+
+def solve3_fft(gx, gy, gz, P: int, M: int, N: int, workers: int | None = None) -> np.ndarray:
+    """Three-dimensional GFC of one volume: L = div E (7-point, backward differences on the
+    torus), v = R(F^-1(F(L) o G^)), u = v[block] - v[0,0,0]. float64, library FFTs."""
+    gx = np.asarray(gx, dtype=np.float64)
+    gy = np.asarray(gy, dtype=np.float64)
+    gz = np.asarray(gz, dtype=np.float64)
+    D, H, W = gx.shape
+    o = block_offset3(D, H, W, P, M, N)
+    L = _divergence3(gx, gy, gz, P, M, N, o)
+    w = workers if workers is not None else cpu_workers()
+    G = green_spectrum3(P, M, N)[:, :, : N // 2 + 1]
+    v = sfft.irfftn(sfft.rfftn(L, workers=w) * G, s=(P, M, N), workers=w)
+    return v[o[0]:o[0] + D, o[1]:o[1] + H, o[2]:o[2] + W] - v[0, 0, 0]
+
+
+def lstsq_torus3(gx, gy, gz, P: int, M: int, N: int) -> np.ndarray:
+    """Dense least squares of the 3-D torus gradient system (Sec. 2.2 in three dimensions),
+    minimum-norm solution aligned to the same corner constant. Tiny tori only."""
+    gx = np.asarray(gx, dtype=np.float64)
+    D, H, W = gx.shape
+    o = block_offset3(D, H, W, P, M, N)
+    n = P * M * N
+    idx = np.arange(n).reshape(P, M, N)
+    rows = []
+    for ax in (2, 1, 0):  # x, y, z forward differences
+        Dm = np.zeros((n, n))
+        nb = np.roll(idx, -1, axis=ax)
+        Dm[idx.ravel(), nb.ravel()] += 1.0
+        Dm[idx.ravel(), idx.ravel()] -= 1.0
+        rows.append(Dm)
+    A = np.vstack(rows)
+    E = []
+    for g in (gx, gy, gz):
+        t = np.zeros((P, M, N))
+        t[o[0]:o[0] + D, o[1]:o[1] + H, o[2]:o[2] + W] = g
+        E.append(t.ravel())
+    v = np.linalg.lstsq(A, np.concatenate(E), rcond=None)[0].reshape(P, M, N)
+    return v[o[0]:o[0] + D, o[1]:o[1] + H, o[2]:o[2] + W] - v[0, 0, 0]

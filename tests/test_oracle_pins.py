@@ -490,3 +490,62 @@ def test_laplacian_of_a_framed_image_reconstructs_it():
     oy, ox = O.block_offset(H, W, M, N)
     v = np.real(np.fft.ifft2(np.fft.fft2(O.embed(L, M, N, oy, ox)) * Gh))
     assert np.max(np.abs((v[oy:oy + H, ox:ox + W] - v[0, 0]) - S)) < 1e-11
+
+
+# ---------------------------------------------------------------- three dimensions
+
+def _framed_volume(rng, D, H, W):
+    """A volume with zero first plane, row and column (padding before the gradient) and its
+    forward-difference gradient (gx, gy, gz) with a zero exterior."""
+    S = rng.normal(size=(D, H, W))
+    S[0, :, :] = 0.0
+    S[:, 0, :] = 0.0
+    S[:, :, 0] = 0.0
+    g = []
+    for ax in (2, 1, 0):
+        Sp = np.concatenate([S, np.zeros_like(np.take(S, [0], axis=ax))], axis=ax)
+        g.append(np.diff(Sp, axis=ax))
+    return S, g[0], g[1], g[2]
+
+
+def test_3d_framed_conservative_volume_reconstructs_exactly():
+    rng = np.random.default_rng(3501)
+    for D, H, W, P, M, N in ((5, 6, 7, 12, 14, 16), (9, 12, 10, 20, 24, 20)):
+        S, gx, gy, gz = _framed_volume(rng, D, H, W)
+        assert np.max(np.abs(O.solve3_fft(gx, gy, gz, P, M, N) - S)) < 1e-12
+
+
+def test_3d_gfc_equals_dense_torus_least_squares():
+    """Sec. 2.2 in three dimensions: the Fourier solve is the least-squares potential."""
+    rng = np.random.default_rng(3502)
+    D, H, W, P, M, N = 3, 4, 3, 6, 6, 6
+    gx, gy, gz = (rng.normal(size=(D, H, W)) for _ in range(3))
+    a = O.solve3_fft(gx, gy, gz, P, M, N)
+    b = O.lstsq_torus3(gx, gy, gz, P, M, N)
+    assert np.max(np.abs(a - b)) < 1e-10
+
+
+def test_3d_green_spectrum_inverts_the_7_point_stencil():
+    """1 / lambda is the spectrum of the pseudo-inverse of the 7-point Laplacian: K * g =
+    delta - 1 / (P M N) (eq. (16) in three dimensions, DC projected out)."""
+    P, M, N = 6, 8, 10
+    g = np.real(np.fft.ifftn(O.green_spectrum3(P, M, N)))
+    Kg = -6 * g
+    for ax in range(3):
+        Kg += np.roll(g, 1, axis=ax) + np.roll(g, -1, axis=ax)
+    d = -np.full((P, M, N), 1.0 / (P * M * N))
+    d[0, 0, 0] += 1.0
+    assert np.max(np.abs(Kg - d)) < 1e-13
+
+
+def test_3d_interior_laplacian_equals_divergence():
+    rng = np.random.default_rng(3503)
+    D, H, W, P, M, N = 8, 9, 10, 18, 18, 20
+    gx, gy, gz = (rng.normal(size=(D, H, W)) for _ in range(3))
+    u = O.solve3_fft(gx, gy, gz, P, M, N)
+    lap = -6 * u[1:-1, 1:-1, 1:-1]
+    for ax in range(3):
+        lap += np.roll(u, 1, axis=ax)[1:-1, 1:-1, 1:-1] + np.roll(u, -1, axis=ax)[1:-1, 1:-1, 1:-1]
+    L = (gx[1:-1, 1:-1, 1:-1] - gx[1:-1, 1:-1, :-2] + gy[1:-1, 1:-1, 1:-1] - gy[1:-1, :-2, 1:-1]
+         + gz[1:-1, 1:-1, 1:-1] - gz[:-2, 1:-1, 1:-1])
+    assert np.max(np.abs(lap - L)) < 1e-11
