@@ -167,6 +167,41 @@ def ragged_bench(torch, gfc, synth, dev, stream, reps):
             "ragged_hbm_frac": pbytes / (ms_r / 1e3) / HBM_PEAK}
 
 
+def volume_bench(torch, gfc, dev, stream, reps, D=128, B=4):
+    """Three-dimensional solve of B volumes D^3 on the default (2D)^3 torus: volumes/s and
+    the algorithmic HBM rate of the five passes."""
+    import math
+    plan = gfc.Plan3(D, D, D).build(dev)
+    g = [torch.randn((B, D, D, D), device=dev) * 0.1 for _ in range(3)]
+    u = torch.empty_like(g[0])
+    ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        plan.solve(*g, out=u, workspace=ws)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(reps):
+        plan.solve(*g, out=u, workspace=ws)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    H = W = D
+    P, N = plan.P, plan.N
+    NH = N // 2 + 1
+    R = H + 1
+    vox = D * H * W
+    bytes_vol = (12.0 * vox + 8.0 * (D + 1) * R * NH          # rows: gx, gy, gz -> T
+                 + 8.0 * (D + 1) * R * NH + 8.0 * P * R * NH  # z forward
+                 + 8.0 * P * R * NH + 8.0 * P * H * NH        # column recursion
+                 + 8.0 * P * R * NH + 8.0 * D * R * NH        # z inverse
+                 + 8.0 * D * H * NH + 4.0 * vox)              # inverse rows -> u
+    return {"workload": f"volume{D}^3_b{B}", "torus": [plan.P, plan.M, plan.N],
+            "volumes_per_s": B / (ms / 1e3), "ms": ms,
+            "hbm_frac": bytes_vol * B / (ms / 1e3) / HBM_PEAK,
+            "bytes_per_volume": bytes_vol}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +211,7 @@ def main():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-color", action="store_true")
     ap.add_argument("--no-edit", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -352,6 +388,9 @@ def main():
         edits["params"] = f"threshold at the median gradient magnitude; gdm alpha 0.5, C ~ U[0,1]"
         result["edit"] = edits
         del C
+
+    if not args.no_volume:
+        result["volume"] = volume_bench(torch, gfc, dev, stream, max(args.steps // 2, 3))
 
     if not args.no_bwd:
         du = torch.randn_like(gx) * 0.1

@@ -254,6 +254,30 @@ int gfc_supported_length(int N);
 /* Human-readable status name. */
 const char* gfc_status_str(gfc_status s);
 
+/*
+ * Volumes: three-dimensional GFC (the method holds in any dimension, eq. (5); the Green's
+ * spectrum is 1/lambda with lambda = -4 sin^2(pi kz/P) - 4 sin^2(pi ky/M) - 4 sin^2(pi kx/N),
+ * the 7-point stencil's symbol, and 0 at the DC bin). A D x H x W volume sits centred in a
+ * P x M x N torus (P = 0: the smallest even 2/3/5-smooth P >= 2D, likewise M, N);
+ * u = v[block] - v[0,0,0]. P, M and N are at most 512 (GFC_E_SIZE otherwise): the 7-point
+ * divergence is transformed in float32 as it stands, with no split of the lowest
+ * frequencies, and the rounding of those bins grows with the square of the longest extent.
+ *   gx, gy, gz : [B][D][H][W] float32 forward-difference fields, zero exterior
+ *   u          : [B][D][H][W] float32
+ * Passes: rows of the 7-point divergence (x), a complex FFT along z, the column recursion
+ * along y per (kz, l), the inverse z FFT, the inverse rows with crop and constant. Forward
+ * only. Errors and conventions as for the two-dimensional entry points.
+ */
+typedef struct gfc_plan3_s* gfc_plan3_t;
+gfc_status gfc_plan3_create(gfc_plan3_t* out, int D, int H, int W, int P, int M, int N,
+                            unsigned flags);
+gfc_status gfc_plan3_get(gfc_plan3_t p, int* D, int* H, int* W, int* P, int* M, int* N);
+gfc_status gfc_green_build3(gfc_plan3_t p, void* stream);
+gfc_status gfc_workspace3_size(gfc_plan3_t p, int B, size_t* bytes);
+gfc_status gfc_solve3_batch(gfc_plan3_t p, const float* gx, const float* gy, const float* gz,
+                            float* u, int B, void* workspace, size_t ws_bytes, void* stream);
+void gfc_plan3_destroy(gfc_plan3_t p);
+
 #ifdef __cplusplus
 }
 #endif

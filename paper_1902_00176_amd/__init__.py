@@ -61,6 +61,13 @@ def lib():
             L.gfc_solve_edit.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, vp, vp, vp, i, vp,
                                          sz, vp]
             L.gfc_solve_laplacian.argtypes = [vp, vp, vp, i, vp, sz, vp]
+            L.gfc_plan3_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, i, u]
+            L.gfc_plan3_get.argtypes = [vp, ip, ip, ip, ip, ip, ip]
+            L.gfc_green_build3.argtypes = [vp, vp]
+            L.gfc_workspace3_size.argtypes = [vp, i, ctypes.POINTER(sz)]
+            L.gfc_solve3_batch.argtypes = [vp, vp, vp, vp, vp, i, vp, sz, vp]
+            L.gfc_plan3_destroy.argtypes = [vp]
+            L.gfc_plan3_destroy.restype = None
             L.gfc_solve_batch_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_solve_backward_stage.argtypes = [vp, i, vp, vp, vp, i, vp, sz, vp]
             L.gfc_plan_set_param.argtypes = [vp, ctypes.c_char_p, i]
@@ -390,6 +397,78 @@ def solve_color(gx, gy, I_mean, I_std, M: int = 0, N: int = 0, **kw):
 def solve_laplacian(L, M: int = 0, N: int = 0, **kw):
     """u from the Laplacian L [..., H+1, W+1] (Algorithm B's input)."""
     return get_plan(L.shape[-2] - 1, L.shape[-1] - 1, M or 0, N or 0).solve_laplacian(L, **kw)
+
+
+class Plan3:
+    """A solver plan for D x H x W volumes on a P x M x N torus (0: default extents).
+    Three-dimensional GFC: the 7-point divergence, the Green's spectrum 1/lambda of the
+    7-point stencil, u = v[block] - v[0,0,0]."""
+
+    def __init__(self, D: int, H: int, W: int, P: int = 0, M: int = 0, N: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        _check(L.gfc_plan3_create(ctypes.byref(h), int(D), int(H), int(W), int(P), int(M),
+                                  int(N), 0), "gfc_plan3_create")
+        self._h = h
+        vals = [ctypes.c_int() for _ in range(6)]
+        _check(L.gfc_plan3_get(h, *[ctypes.byref(v) for v in vals]), "gfc_plan3_get")
+        self.D, self.H, self.W, self.P, self.M, self.N = [v.value for v in vals]
+        self._built_on = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.gfc_plan3_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def build(self, device=None, stream=None):
+        import torch
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self._built_on is None:
+            with torch.cuda.device(dev):
+                _check(lib().gfc_green_build3(self._h, _stream_ptr(torch, dev, stream)),
+                       "gfc_green_build3")
+            self._built_on = dev
+        elif self._built_on != dev:
+            raise ValueError(f"plan built on {self._built_on}, used on {dev}")
+        return self
+
+    def workspace_size(self, B: int) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().gfc_workspace3_size(self._h, int(B), ctypes.byref(n)), "gfc_workspace3_size")
+        return n.value
+
+    def solve(self, gx, gy, gz, out=None, workspace=None, stream=None):
+        import torch
+        dev = gx.device
+        shape = (self.D, self.H, self.W)
+        for t in (gx, gy, gz):
+            if t.device != dev or t.dtype != torch.float32 or dev.type != "cuda":
+                raise TypeError("volume fields must be float32 CUDA tensors on one device")
+            if tuple(t.shape[-3:]) != shape or t.shape != gx.shape:
+                raise ValueError(f"expected [..., {self.D}, {self.H}, {self.W}], got {tuple(t.shape)}")
+        self.build(dev)
+        gx, gy, gz = gx.contiguous(), gy.contiguous(), gz.contiguous()
+        B = gx.numel() // (self.D * self.H * self.W)
+        u = out if out is not None else torch.empty_like(gx)
+        need = self.workspace_size(B)
+        ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=dev)
+        with torch.cuda.device(dev):
+            _check(lib().gfc_solve3_batch(self._h, gx.data_ptr(), gy.data_ptr(), gz.data_ptr(),
+                                          u.data_ptr(), B, ws.data_ptr(),
+                                          ws.numel() * ws.element_size(),
+                                          _stream_ptr(torch, dev, stream)), "gfc_solve3_batch")
+        return u
+
+
+def solve3(gx, gy, gz, P: int = 0, M: int = 0, N: int = 0, **kw):
+    """u = GFC(gx, gy, gz) for float32 CUDA volumes [..., D, H, W]."""
+    D, H, W = gx.shape[-3:]
+    return Plan3(D, H, W, P, M, N).solve(gx, gy, gz, **kw)
 
 
 EDIT_THRESHOLD = 1

@@ -63,6 +63,18 @@ def default_lengths():
     return sorted(set(out))
 
 
+def z_lengths():
+    """Volume depths P (the torus along z) compiled into the library: every even
+    2/3/5-smooth P in [4, 512] that splits into two factors <= 64."""
+    return [p for p in range(4, 513, 2) if smooth235(p) and choose_factors(p) is not None]
+
+
+def _z_split(P: int):
+    """(P1, P2) for the z transform: choose_factors where it applies, else 2 x P/2."""
+    f = choose_factors(P)
+    return f if f is not None else (2, P // 2)
+
+
 def _lengths_from_env():
     v = os.environ.get("GFC_ROW_LENGTHS")
     if not v:
@@ -96,7 +108,17 @@ def generate(lengths):
              f"  return nullptr;\n}}\n}}  // namespace gfc\n")
     tpath = os.path.join(GEN, "row_table.hip")
     _write_if_changed(tpath, table)
-    return srcs + [tpath]
+    # z transforms of volumes: one unit for all depths (small kernels)
+    zl = z_lengths()
+    zt = ('#include "gfc_zfft.h"\nnamespace gfc {\n'
+          "static const ZKernels kZ[] = {\n    "
+          + ",\n    ".join(f"GFC_Z_ENTRY({_z_split(p)[0]}, {_z_split(p)[1]})" for p in zl)
+          + "};\n"
+          f"const ZKernels* find_z_kernels(int P) {{\n  for (int i = 0; i < {len(zl)}; ++i)\n"
+          "    if (kZ[i].P == P) return &kZ[i];\n  return nullptr;\n}\n}  // namespace gfc\n")
+    zpath = os.path.join(GEN, "z_table.hip")
+    _write_if_changed(zpath, zt)
+    return srcs + [tpath, zpath]
 
 
 def _write_if_changed(path, text):

@@ -60,23 +60,31 @@ ColGeom col_geometry(int R, int M, int r0, int rows, int C_req) {
 
 namespace {
 
+}  // namespace
+
+// Per column (kz, l) of a P x M x N problem (P = 1 for images): the recursion constants for
+// beta = 4 sin^2(pi l / N) + 4 sin^2(pi kz / P), the output scale 1 / (N P) (the row and z
+// inverse transforms are unnormalised), and the reference weights for the corner at
+// (z0, r0, c0). Output [P][NH].
 void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
-                   std::vector<ColConst>& out) {
+                   std::vector<ColConst>& out, int P, int z0) {
   const int R = g.Rp;
-  out.assign(p.NH, ColConst{});
+  out.assign(size_t(P) * p.NH, ColConst{});
   const double M = p.M, N = p.N;
+  for (int kz = 0; kz < P; ++kz)
   for (int l = 0; l < p.NH; ++l) {
     ColConst k{};
-    if (l == 0) {
+    if (l == 0 && kz == 0) {
       k.rho = 1.0;
       k.inv_rho = 1.0;
-      k.outs = 1.0 / N;
+      k.outs = 1.0 / (N * P);
       k.kseg = g.nseg;
-      out[l] = k;
+      out[size_t(kz) * p.NH + l] = k;
       continue;
     }
     const double sn = std::sin(kPi * double(l) / N);
-    const double beta = 4.0 * sn * sn;
+    const double sz = std::sin(kPi * double(kz) / double(P));
+    const double beta = 4.0 * sn * sn + 4.0 * sz * sz;
     const double sq = std::sqrt(beta + 0.25 * beta * beta);
     const double den = 1.0 + 0.5 * beta + sq;
     const double rho = 1.0 / den;
@@ -88,7 +96,7 @@ void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
     k.omr = (0.5 * beta + sq) / den;
     const double one_m_r2 = k.omr * (1.0 + rho);
     const double inv1mrM = 1.0 / one_minus_pw(M);
-    k.outs = -rho / N;
+    k.outs = -rho / (N * P);
     k.rhoL = pw(g.Lseg);
     k.rhoLl = pw(g.Llast);
     // rho^d < 2^-64 for d >= dmax rows; carries from further than that are dropped
@@ -107,15 +115,18 @@ void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
     k.cgd = pw(M - r0) * inv1mrM;
     k.cTd = pw(r0 - R) * one_minus_pw(2.0 * (M - r0)) / one_m_r2 * inv1mrM;
     if (forward) {
+      // angle 2 pi (l c0 / N + kz z0 / P), reduced exactly as one fraction of N P
       double c, s;
-      cs2pi(long(l) * p.c0, p.N, c, s);
-      const double wgt = (2 * l == p.N) ? 1.0 : 2.0;
+      cs2pi(long(l) * p.c0 * P + long(kz) * z0 * p.N, long(p.N) * P, c, s);
+      const double wgt = (l == 0 || 2 * l == p.N) ? 1.0 : 2.0;  // Hermitian pairs in l
       k.wre = wgt * k.outs * c;
       k.wim = wgt * k.outs * s;
     }
-    out[l] = k;
+    out[size_t(kz) * p.NH + l] = k;
   }
 }
+
+namespace {
 
 
 // launch geometry that follows from the sizes and the tunable parameters
@@ -278,8 +289,8 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
     dsh[l] = f2{float(c), float(-s)};    // e^{-2 pi i l c0 / N}
   }
   std::vector<ColConst> ccf, ccb;
-  fill_colconst(*p, p->gf, true, ccf);
-  fill_colconst(*p, p->gb, false, ccb);
+  fill_colconst(*p, p->gf, true, ccf, 1, 0);
+  fill_colconst(*p, p->gb, false, ccb, 1, 0);
 
   size_t off = 0;
   const size_t o_twA = off; off = align256(off + twA.size() * sizeof(f2));
@@ -562,6 +573,205 @@ void gfc_plan_destroy(gfc_plan_t p) {
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
   }
   delete p;
+}
+
+
+// ---- volumes (n-D GFC, three dimensions) --------------------------------------------------
+
+}  // extern "C"
+
+constexpr int kMaxVolumeExtent = 512;
+
+struct gfc_plan3_s {
+  gfc_plan_s* p2 = nullptr;  // the (y, x) part: H, W, M, N, row kernels, column geometry
+  int D = 0, P = 0, oz = 0, z0 = 0;
+  const gfc::ZKernels* zk = nullptr;
+  bool built = false;
+  void* dmem = nullptr;
+  gfc::ColConst* cc = nullptr;  // [P][NH]
+  gfc::f2* tw = nullptr;        // [P1][P2]
+};
+
+namespace {
+struct Ws3 {
+  size_t t, side, red, total;
+};
+Ws3 ws3_layout(const gfc_plan3_s* q, int B) {
+  const gfc_plan_s* p = q->p2;
+  Ws3 w{};
+  const size_t vols = size_t(B) * q->P;
+  w.t = 0;
+  w.side = align256(vols * size_t(p->H + 1) * p->NHP * sizeof(f2));
+  w.red = w.side + align256(vols * size_t(p->H) * p->KP * sizeof(f2));
+  w.total = w.red + align256(vols * size_t(p->ntiles_f) * sizeof(double));
+  return w;
+}
+}  // namespace
+
+extern "C" {
+
+gfc_status gfc_plan3_create(gfc_plan3_t* out, int D, int H, int W, int P, int M, int N,
+                            unsigned flags) {
+  if (!out) return GFC_E_ARG;
+  *out = nullptr;
+  if (D < 1 || P < 0 || flags != GFC_FLAG_NONE) return GFC_E_ARG;
+  if (P == 0) P = smooth_at_least(2L * D);
+  if (P < D + 2) return GFC_E_SIZE;
+  const ZKernels* zk = find_z_kernels(P);
+  if (!zk) return GFC_E_SIZE;
+  gfc_plan_t p2 = nullptr;
+  const gfc_status st = gfc_plan_create(&p2, H, W, M, N, flags);
+  if (st != GFC_OK) return st;
+  // Volumes transform the literal 7-point divergence in float32: there is no split of the
+  // lowest frequencies into their x-, y- and z-parts as for images, and the rounding of the
+  // lowest bins grows with the square of the longest torus extent. Up to 512 along every
+  // axis the error stays a few 1e-6; longer axes are refused.
+  if (P > kMaxVolumeExtent || p2->M > kMaxVolumeExtent || p2->N > kMaxVolumeExtent) {
+    gfc_plan_destroy(p2);
+    return GFC_E_SIZE;
+  }
+  // a volume's (P planes) spectra must stay addressable with 32-bit offsets per plane set
+  if ((long long)P * (p2->H + 1) * p2->NHP * 8 >= (1LL << 31) ||
+      (long long)D * H * W * 4 >= (1LL << 30)) {
+    gfc_plan_destroy(p2);
+    return GFC_E_SIZE;
+  }
+  p2->K = 0;  // only the DC column (kz, l) = (0, 0) takes the split input
+  derive_geometry(p2);
+  auto* q = new (std::nothrow) gfc_plan3_s;
+  if (!q) {
+    gfc_plan_destroy(p2);
+    return GFC_E_OOM;
+  }
+  q->p2 = p2;
+  q->D = D;
+  q->P = P;
+  q->oz = (P - D) / 2;
+  q->z0 = P - q->oz;  // grid corner relative to the volume at the origin
+  q->zk = zk;
+  *out = q;
+  return GFC_OK;
+}
+
+gfc_status gfc_plan3_get(gfc_plan3_t q, int* D, int* H, int* W, int* P, int* M, int* N) {
+  if (!q) return GFC_E_ARG;
+  if (D) *D = q->D;
+  if (P) *P = q->P;
+  return gfc_plan_get(q->p2, H, W, M, N, nullptr, nullptr);
+}
+
+gfc_status gfc_green_build3(gfc_plan3_t q, void* stream) {
+  if (!q) return GFC_E_ARG;
+  if (q->built) return GFC_OK;
+  gfc_status st = gfc_green_build(q->p2, stream);
+  if (st != GFC_OK) return st;
+  const int P = q->P, P1 = q->zk->P1, P2 = q->zk->P2;
+  std::vector<ColConst> cc;
+  fill_colconst(*q->p2, q->p2->gf, true, cc, P, q->z0);
+  std::vector<f2> tw(size_t(P1) * P2);
+  for (int k1 = 0; k1 < P1; ++k1)
+    for (int j = 0; j < P2; ++j) {
+      double c, s;
+      cs2pi(long(k1) * j, P, c, s);
+      tw[size_t(k1) * P2 + j] = f2{float(c), float(-s)};
+    }
+  const size_t o_cc = 0;
+  const size_t o_tw = align256(cc.size() * sizeof(ColConst));
+  const size_t total = o_tw + align256(tw.size() * sizeof(f2));
+  std::vector<unsigned char> host(total, 0);
+  std::memcpy(host.data() + o_cc, cc.data(), cc.size() * sizeof(ColConst));
+  std::memcpy(host.data() + o_tw, tw.data(), tw.size() * sizeof(f2));
+  void* d = nullptr;
+  if (hipMalloc(&d, total) != hipSuccess) return GFC_E_OOM;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(d, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(d);
+    return GFC_E_HIP;
+  }
+  q->dmem = d;
+  q->cc = reinterpret_cast<ColConst*>(static_cast<unsigned char*>(d) + o_cc);
+  q->tw = reinterpret_cast<f2*>(static_cast<unsigned char*>(d) + o_tw);
+  q->built = true;
+  return GFC_OK;
+}
+
+gfc_status gfc_workspace3_size(gfc_plan3_t q, int B, size_t* bytes) {
+  if (!q || !bytes || B < 0) return GFC_E_ARG;
+  *bytes = ws3_layout(q, B).total;
+  return GFC_OK;
+}
+
+gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, const float* gz,
+                            float* u, int B, void* workspace, size_t ws_bytes, void* stream) {
+  if (!q || B < 0) return GFC_E_ARG;
+  if (!q->built) return GFC_E_NOT_BUILT;
+  if (B == 0) return GFC_OK;
+  if (!gx || !gy || !gz || !u || !workspace) return GFC_E_ARG;
+  const Ws3 w = ws3_layout(q, B);
+  if (ws_bytes < w.total) return GFC_E_WORKSPACE;
+  gfc_plan_s* p = q->p2;
+  auto* ws = static_cast<unsigned char*>(workspace);
+  f2* T = reinterpret_cast<f2*>(ws + w.t);
+  f2* SB = reinterpret_cast<f2*>(ws + w.side);
+  double* partial = reinterpret_cast<double*>(ws + w.red);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int D = q->D, P = q->P;
+  const long long plane = (long long)(p->H + 1) * p->NHP;
+  // 1. rows of the 7-point divergence, every slice z in [0, D] of every volume
+  RowFwdArgs f = row_fwd_args(p, gx, gy, T, SB);
+  f.edit = kIn3D;
+  f.gz = gz;
+  f.zd = D;
+  f.zp = P;
+  gfc_status st = hip_status(p->rk->fwd(f, B * (D + 1), s));
+  if (st != GFC_OK) return st;
+  // 2. z transform: D + 1 planes in, P planes out
+  ZfftArgs z{};
+  z.T = T;
+  z.tw = q->tw;
+  z.R = p->H + 1;
+  z.NH = p->NH;
+  z.NHP = p->NHP;
+  z.plane = plane;
+  z.vol_stride = plane * P;
+  z.din = D + 1;
+  z.dout = P;
+  st = hip_status(q->zk->run(z, -1, B, s));
+  if (st != GFC_OK) return st;
+  // 3. the DC column's running sums; 4. the column pass per (kz, l)
+  st = hip_status(launch_sb_volume(T, SB, p->H, p->KP, P, p->NHP, plane * P,
+                                   (long long)p->H * p->KP, B, s));
+  if (st != GFC_OK) return st;
+  ColFwdArgs c = col_fwd_args(p, T, SB, partial);
+  c.cc = q->cc;
+  c.zp = P;
+  st = hip_status(launch_col_fwd(c, B * P, s, p->side, p->ev_fork, p->ev_join));
+  if (st != GFC_OK) return st;
+  // 5. inverse z transform: P planes in, the D planes of the volume out
+  z.din = P;
+  z.dout = D;
+  st = hip_status(q->zk->run(z, +1, B, s));
+  if (st != GFC_OK) return st;
+  // 6. inverse rows of every slice z < D, crop and the corner constant
+  RowInvArgs v = row_inv_args(p, T, u, partial);
+  v.zd = D;
+  v.zp = P;
+  v.nparts = P * p->ntiles_f;
+  return hip_status(p->rk->inv(v, B * D, s));
+}
+
+void gfc_plan3_destroy(gfc_plan3_t q) {
+  if (!q) return;
+  if (q->dmem) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (q->p2->device >= 0 && cur != q->p2->device) (void)hipSetDevice(q->p2->device);
+    (void)hipFree(q->dmem);
+    if (cur >= 0 && cur != q->p2->device) (void)hipSetDevice(cur);
+  }
+  gfc_plan_destroy(q->p2);
+  delete q;
 }
 
 }  // extern "C"

@@ -122,7 +122,9 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   const bool active = s < nseg;
   const int l = tile * C + c;
   const bool col_ok = active && l < p.NH;
-  const bool dcol = LOWTILE && col_ok && l == 0;
+  // volumes: image b is plane kz of a volume; only (kz, l) = (0, 0) is the DC column
+  const int kz = p.zp > 1 ? b % p.zp : 0;
+  const bool dcol = LOWTILE && col_ok && l == 0 && kz == 0;
   const bool low = LOWTILE && col_ok && l <= p.K;
   const int p0 = s * LMAX;
   const int Ls = (TAIL && s == last) ? p.Llast : LMAX;
@@ -132,7 +134,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   const int vT = col_ok ? (p0 * p.NHP + l) * 8 : kOOB;
   const int vX = (col_ok && !dcol) ? vT : kOOB;  // column 0 has a = 0
 
-  const ColConst* kp = p.cc + (col_ok ? l : 0);
+  const ColConst* kp = p.cc + kz * p.NH + (col_ok ? l : 0);
   const double rho = dcol ? 1.0 : kp->rho;
 
   // ---- 1. load the segment, causal sweep from a zero state ----

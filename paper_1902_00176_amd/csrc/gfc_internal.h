@@ -19,7 +19,8 @@ constexpr int kLowBins = 4;  // K: row frequencies l <= K arrive at the column p
 // threshold (Sec. 3.2.3): E kept where fl(fl(gx^2) + fl(gy^2)) >= tau2, else 0;
 // GDM (eq. (26)): E scaled to |E|^(1-alpha) C^alpha, orientation kept, 0 where E = 0.
 // kInLaplacian: the input is the divergence itself, L [B][H+1][W+1] (Algorithm B's input).
-enum { kEditNone = 0, kEditThreshold = 1, kEditGdm = 2, kInLaplacian = 3 };
+// kIn3D: a slice z of a volume; the divergence also takes -gz[z-1] + gz[z] (7-point).
+enum { kEditNone = 0, kEditThreshold = 1, kEditGdm = 2, kInLaplacian = 3, kIn3D = 4 };
 struct RowFwdArgs {
   const float* gx;
   const float* gy;
@@ -35,6 +36,10 @@ struct RowFwdArgs {
   int ppw;            // pairs of L rows per slot
   int npairs;         // ceil((H+1) / 2)
   long long img_in, img_t1, img_sb;
+  // volumes (kIn3D): the launch's image index runs over (volume, z) with z in [0, zd]; gx,
+  // gy, gz are [B][zd][H][W]; T1 planes are [B][zp][H+1][NHP] (plane z of each volume)
+  const float* gz;
+  int zd, zp;
 };
 
 // Inverse row pass: rows y in [0, H) of T2 (already scaled by 1/N), two rows per complex
@@ -50,6 +55,9 @@ struct RowInvArgs {
   int ppw;            // row pairs per slot
   long long img_t2, img_u;
   double* mom;        // [B][gridDim.x][2]: sums of u and u^2 per workgroup, or null
+  // volumes: the image index runs over (volume, z), z < zd; T2 planes [B][zp][H+1][NHP],
+  // partials [B][nparts] per volume (zd = zp = 1 for images)
+  int zd, zp;
 };
 
 // Laplacian input: SB[y][0] <- sum_{y' <= y} SB[y'][0] for y in [0, H) of every image, so the
@@ -135,6 +143,9 @@ struct ColFwdArgs {
   int H, M, NH, NHP, K, KP, r0;
   int C, nseg, Lseg, Llast, Rp;   // R = H + 1 rows of input
   long long img_t, img_sb;
+  // volumes: the image index runs over (volume, kz); constants cc[kz][NH]; the DC path only
+  // at kz = 0 (zp = 1 for images)
+  int zp;
 };
 
 struct ColBwdArgs {
@@ -176,6 +187,23 @@ struct RgRowInv {
   RowInvArgs a;
   long long out, t, red;
 };
+
+// ---- z transforms of volumes -------------------------------------------------------------
+struct ZfftArgs {
+  f2* T;               // spectra of one volume at T + vol * vol_stride: [P][R][NHP]
+  const f2* tw;        // [P1][P2]: w_P^(k1 j), forward sign
+  int R, NH, NHP;      // rows per plane, row frequencies used, row stride
+  int din, dout;       // planes read (the rest are zero), planes written
+  long long plane, vol_stride;  // elements per plane, per volume
+};
+struct ZKernels {
+  int P, P1, P2;
+  hipError_t (*run)(const ZfftArgs&, int sign, int B, hipStream_t);
+};
+const ZKernels* find_z_kernels(int P);
+// volumes: SB[vol * P + kz][y][0] = (kz == 0) ? sum_{y' <= y} T[vol][0][y'][0] : 0, y < H
+hipError_t launch_sb_volume(const f2* T, f2* SB, int H, int KP, int P, int NHP,
+                            long long vol_stride, long long img_sb, int B, hipStream_t s);
 
 // launchers (defined in the kernel files)
 struct RowKernels {

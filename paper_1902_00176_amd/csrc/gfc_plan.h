@@ -98,6 +98,9 @@ inline RowFwdArgs row_fwd_args(const gfc_plan_s* p, const float* gx, const float
   a.img_in = (long long)p->H * p->W;
   a.img_t1 = (long long)(p->H + 1) * p->NHP;
   a.img_sb = (long long)p->H * p->KP;
+  a.gz = nullptr;
+  a.zd = 0;
+  a.zp = 1;
   return a;
 }
 
@@ -122,6 +125,7 @@ inline ColFwdArgs col_fwd_args(const gfc_plan_s* p, f2* T, const f2* SB, double*
   c.nparts = p->ntiles_f;
   c.img_t = (long long)(p->H + 1) * p->NHP;
   c.img_sb = (long long)p->H * p->KP;
+  c.zp = 1;
   return c;
 }
 
@@ -140,6 +144,8 @@ inline RowInvArgs row_inv_args(const gfc_plan_s* p, const f2* T, float* u,
   v.img_t2 = (long long)(p->H + 1) * p->NHP;
   v.img_u = (long long)p->H * p->W;
   v.mom = nullptr;
+  v.zd = 1;
+  v.zp = 1;
   return v;
 }
 

@@ -338,6 +338,57 @@ __device__ __forceinline__ void lap_load(cx (&a)[N1], const Rows& r, int W) {
   }
 }
 
+// Volumes: slice z of the 7-point divergence, L = dx Ex + dy Ey + (Ez[z] - Ez[z-1]).
+// Uniform rows: one descriptor per (field, row); gz of planes z and z - 1.
+struct VolRowsU {
+  rsrc_t x0, x1, ym, y0, y1, z0, z1, zm0, zm1;
+  int vb;
+};
+template <int N1, int N2, int Y1>
+__device__ __forceinline__ void vol_block(cx (&a)[N1], const VolRowsU& r, int W) {
+  const int v = r.vb + N2 * Y1 * 4;
+  const float gx0 = bld1(r.x0, v, 0), gx0m = bld1(r.x0, v - 4, 0);
+  const float gx1 = bld1(r.x1, v, 0), gx1m = bld1(r.x1, v - 4, 0);
+  const float gym = bld1(r.ym, v, 0), gy0 = bld1(r.y0, v, 0), gy1 = bld1(r.y1, v, 0);
+  const float gz0 = bld1(r.z0, v, 0), gz1 = bld1(r.z1, v, 0);
+  const float gzm0 = bld1(r.zm0, v, 0), gzm1 = bld1(r.zm1, v, 0);
+  a[Y1] = {((gx0 - gx0m) + (gy0 - gym)) + (gz0 - gzm0),
+           ((gx1 - gx1m) + (gy1 - gy0)) + (gz1 - gzm1)};
+}
+// Several slots per wavefront: per-lane offsets into volume-wide descriptors.
+struct VolRowsL {
+  rsrc_t gx, gy, gz;
+  int zm, z0, z1;     // plane z: rows y0 - 1, y0, y0 + 1 (kOOB outside)
+  int zz0, zz1;       // plane z - 1: rows y0, y0 + 1 (kOOB outside)
+  int z0m, z1m;       // plane z, x - 1 at y1 = 0 (kOOB for lane 0)
+  int lane;
+};
+template <int N1, int N2, int Y1>
+__device__ __forceinline__ void vol_block(cx (&a)[N1], const VolRowsL& r, int W) {
+  const int lim = W - N2 * Y1;
+  const bool xin = r.lane < lim, xmin = r.lane <= lim;
+  constexpr int so = N2 * Y1 * 4, som = Y1 == 0 ? 0 : N2 * Y1 * 4 - 4;
+  const int o0 = xin ? r.z0 : kOOB, o1 = xin ? r.z1 : kOOB, om = xin ? r.zm : kOOB;
+  const int q0 = xin ? r.zz0 : kOOB, q1 = xin ? r.zz1 : kOOB;
+  const int p0 = xmin ? (Y1 == 0 ? r.z0m : r.z0) : kOOB;
+  const int p1 = xmin ? (Y1 == 0 ? r.z1m : r.z1) : kOOB;
+  const float gx0 = bld1(r.gx, o0, so), gx0m = bld1(r.gx, p0, som);
+  const float gx1 = bld1(r.gx, o1, so), gx1m = bld1(r.gx, p1, som);
+  const float gym = bld1(r.gy, om, so), gy0 = bld1(r.gy, o0, so), gy1 = bld1(r.gy, o1, so);
+  const float gz0 = bld1(r.gz, o0, so), gz1 = bld1(r.gz, o1, so);
+  const float gzm0 = bld1(r.gz, q0, so), gzm1 = bld1(r.gz, q1, so);
+  a[Y1] = {((gx0 - gx0m) + (gy0 - gym)) + (gz0 - gzm0),
+           ((gx1 - gx1m) + (gy1 - gy0)) + (gz1 - gzm1)};
+}
+template <int N1, int N2, int NB, int Y1, class Rows>
+__device__ __forceinline__ void vol_load(cx (&a)[N1], const Rows& r, int W) {
+  if constexpr (Y1 < N1) {
+    if constexpr (Y1 < NB) vol_block<N1, N2, Y1>(a, r, W);
+    else a[Y1] = {0.f, 0.f};
+    vol_load<N1, N2, NB, Y1 + 1>(a, r, W);
+  }
+}
+
 // blocks y1 < NB carry the support [0, W]; the rest of a[] is zero
 template <int N1, int N2, int NB, int Y1, int EDIT = kEditNone, class Rows>
 __device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
@@ -372,7 +423,15 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
   float* im = s_lds[slot] + PLANE;
   const float* gxi = p.gx + b * p.img_in;
   const float* gyi = p.gy + b * p.img_in;
-  const rsrc_t rT1 = make_buf(p.T1 + b * p.img_t1, p.img_t1 * 8);
+  // volumes: b runs over (volume, z <= zd); the T1 plane is z of zp
+  const int vz = EDIT == kIn3D ? b % (p.zd + 1) : 0;
+  const long long tplane = EDIT == kIn3D ? (long long)(b / (p.zd + 1)) * p.zp + vz : b;
+  const long long vplane = EDIT == kIn3D ? (long long)(b / (p.zd + 1)) * p.zd + vz : b;
+  if constexpr (EDIT == kIn3D) {
+    gxi = p.gx + vplane * p.img_in;
+    gyi = p.gy + vplane * p.img_in;
+  }
+  const rsrc_t rT1 = make_buf(p.T1 + tplane * p.img_t1, p.img_t1 * 8);
   const rsrc_t rSB = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
   const rsrc_t rtw = make_buf(p.twA, (long long)C::N * 8);
   const rsrc_t rtl = make_buf(p.twL, (long long)2 * (KL + 1) * C::G * 8);
@@ -397,7 +456,36 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     auto off = [&](int y) {
       return (ok && lane < N2 && y >= 0 && y < p.H) ? (y * p.W + lane) * 4 : kOOB;
     };
-    if constexpr (EDIT == kInLaplacian && SLOTS == 1) {
+    if constexpr (EDIT == kIn3D && SLOTS == 1) {
+      // planes z (z < zd) and z - 1 (z >= 1) of this volume; rows outside read 0
+      const bool pz = vz < p.zd, pm = vz >= 1;
+      const float* gzi = p.gz + vplane * p.img_in;
+      auto prow = [&](const float* img, bool plane_ok, int y) {
+        const bool in = plane_ok && ok && y >= 0 && y < p.H;
+        return make_buf(img + (in ? (long long)y * p.W : 0), in ? (long long)p.W * 4 : 0);
+      };
+      const VolRowsU rows{prow(gxi, pz, y0), prow(gxi, pz, y0 + 1), prow(gyi, pz, y0 - 1),
+                          prow(gyi, pz, y0), prow(gyi, pz, y0 + 1), prow(gzi, pz, y0),
+                          prow(gzi, pz, y0 + 1), prow(gzi - p.img_in, pm, y0),
+                          prow(gzi - p.img_in, pm, y0 + 1), (lane < N2 ? lane * 4 : kOOB) + tz};
+      vol_load<N1, N2, NB, 0>(a, rows, p.W);
+    } else if constexpr (EDIT == kIn3D) {
+      const bool pz = vz < p.zd, pm = vz >= 1;
+      const float* gzi = p.gz + vplane * p.img_in;
+      // descriptors from plane z - 1 (when it exists) so both planes are in range
+      const long long lo = pm ? p.img_in : 0;
+      auto voff = [&](bool plane_ok, int plane, int y) {
+        return (plane_ok && ok && lane < N2 && y >= 0 && y < p.H)
+                   ? int(plane * p.img_in + y * p.W + lane) * 4 : kOOB;
+      };
+      const int zp1 = pm ? 1 : 0;  // plane z is the second plane of the descriptors
+      const int z0 = voff(pz, zp1, y0), z1 = voff(pz, zp1, y0 + 1);
+      const VolRowsL rows{make_buf(gxi - lo, (lo + p.img_in) * 4), make_buf(gyi - lo, (lo + p.img_in) * 4),
+                          make_buf(gzi - lo, (lo + p.img_in) * 4), voff(pz, zp1, y0 - 1), z0, z1,
+                          voff(pm, 0, y0), voff(pm, 0, y0 + 1),
+                          lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
+      vol_load<N1, N2, NB, 0>(a, rows, p.W + tz);
+    } else if constexpr (EDIT == kInLaplacian && SLOTS == 1) {
       const float* li = p.C + b * (long long)(p.H + 1) * (p.W + 1);
       auto lrow = [&](int y) {
         const bool in = ok && y <= p.H;
@@ -439,9 +527,11 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     }
 
     // lane factors w_N^(l j) (Ex also times 1 - w_N^l), then the sums over the lanes
-    constexpr int NVL = EDIT == kInLaplacian ? 0 : (NV + C::G - 1) / C::G;
+    // a given Laplacian or a volume slice: every bin comes from the FFT (no split)
+    constexpr bool FULLBINS = EDIT == kInLaplacian || EDIT == kIn3D;
+    constexpr int NVL = FULLBINS ? 0 : (NV + C::G - 1) / C::G;
     float lowsum[NVL > 0 ? NVL : 1];
-    if constexpr (EDIT != kInLaplacian) {
+    if constexpr (!FULLBINS) {
 #pragma unroll
     for (int l = 0; l <= KL; ++l) {
       const f2b wy = bld2(rtl, lane * 8, tz + (KL + 1 + l) * C::G * 8);
@@ -475,7 +565,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
       }
     }
     slot_sync();
-    }  // EDIT != kInLaplacian
+    }  // !FULLBINS
 
     fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
 
@@ -485,9 +575,10 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
 #pragma unroll
     for (int i = 0; i < C::NI; ++i) {
       const int l = lane + C::G * i;
-      if constexpr (EDIT == kInLaplacian) {
-        // every bin of L^ goes to T1; the split side array gets (0 for l > 0 and) the DC
-        // bin, turned into its running sum over the rows by launch_sb_prefix
+      if constexpr (FULLBINS) {
+        // every bin of L^ goes to T1. Laplacian input: the split side array gets (0 for
+        // l > 0 and) the DC bin, turned into its running sum over the rows by
+        // launch_sb_prefix; volumes build theirs after the z transform
         if (ok && l < C::NH) {
           const int m = (l == 0) ? 0 : C::N - l;
           const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
@@ -495,7 +586,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
           const cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
           bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
           if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
-          if (l <= KL) {
+          if (EDIT == kInLaplacian && l <= KL) {
             const bool dc = l == 0;
             if (y0 < p.H) bst2(rSB, dc ? A.x : 0.f, dc ? A.y : 0.f, (y0 * p.KP + l) * 8, 0);
             if (y0 + 1 < p.H) bst2(rSB, dc ? B.x : 0.f, dc ? B.y : 0.f, ((y0 + 1) * p.KP + l) * 8, 0);
@@ -567,14 +658,16 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) 
   const int lane = threadIdx.x % C::G;
   float* re = s_re[slot];
   float* im = s_im[slot];
-  const rsrc_t rT2 = make_buf(p.T2 + b * p.img_t2, p.img_t2 * 8);
+  // image b, or slice z = b % zd of volume b / zd (its spectra are plane z of zp)
+  const int vol = b / p.zd;
+  const rsrc_t rT2 = make_buf(p.T2 + ((long long)vol * p.zp + b % p.zd) * p.img_t2, p.img_t2 * 8);
   const rsrc_t ru = make_buf(p.u + b * p.img_u, p.img_u * 4);
   const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
 
   // v_ref = sum of the column pass's per-tile partials: lane-strided sums, then a fixed-order
   // butterfly across the slot (every lane ends with the same, deterministic total)
   double vr = 0.0;
-  for (int j = lane; j < p.nparts; j += C::G) vr += p.partial[(long long)b * p.nparts + j];
+  for (int j = lane; j < p.nparts; j += C::G) vr += p.partial[(long long)vol * p.nparts + j];
 #pragma unroll
   for (int off = C::G / 2; off > 0; off >>= 1) vr += __shfl_xor(vr, off, C::G);
   const float vref = float(vr);
@@ -843,6 +936,10 @@ struct RowLaunch {
       case kInLaplacian:
         if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kInLaplacian>), grid, blk, 0, s, a);
         else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kInLaplacian>), grid, blk, 0, s, a);
+        break;
+      case kIn3D:
+        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kIn3D>), grid, blk, 0, s, a);
+        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kIn3D>), grid, blk, 0, s, a);
         break;
       default:
         if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);

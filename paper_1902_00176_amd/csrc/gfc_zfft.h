@@ -1,0 +1,111 @@
+// gfc_zfft.h - FFTs along z for volumes: the third axis of the n-D solve (eq. (5) holds in
+// any dimension). The spectra of a volume are planes [P][R][NHP] (z, row y, row frequency l);
+// the transform runs over z for every (y, l). A workgroup takes one row y and a tile of TL
+// consecutive l: coalesced loads of TL * 8 bytes per plane into LDS, one four-step FFT of
+// length P = P1 * P2 per slot of G lanes (as the row passes), coalesced stores.
+#pragma once
+#include "gfc_buf.h"
+#include "gfc_dft.h"
+#include "gfc_internal.h"
+
+namespace gfc {
+
+template <int P1, int P2>
+struct ZCfg {
+  static constexpr int P = P1 * P2;
+  static constexpr int G = P1 > P2 ? (P1 <= 8 ? 8 : P1 <= 16 ? 16 : P1 <= 32 ? 32 : 64)
+                                   : (P2 <= 8 ? 8 : P2 <= 16 ? 16 : P2 <= 32 ? 32 : 64);
+  static constexpr int SA = (P2 % 2 == 0) ? P2 + 1 : P2;  // odd LDS stride of the transpose
+  static constexpr int S = (P1 * SA > P) ? P1 * SA : P;     // floats per plane per slot
+  static constexpr int TL = (2 * S * 4 * 16 <= 48 * 1024) ? 16 : 8;  // columns per workgroup
+};
+
+// din input planes (the rest are zero) -> dout output planes; SIGN -1 forward, +1 inverse
+// (unnormalised). In place: every column is read completely before it is written.
+template <int P1, int P2, int SIGN>
+__global__ void __launch_bounds__((ZCfg<P1, P2>::TL * ZCfg<P1, P2>::G))
+k_zfft(ZfftArgs a) {
+  using C = ZCfg<P1, P2>;
+  constexpr int P = C::P, G = C::G, TL = C::TL, NT = TL * G;
+  __shared__ float s_lds[TL][2 * C::S];
+  const int t = threadIdx.x;
+  const int y = blockIdx.y, vol = blockIdx.z;
+  const int l0 = blockIdx.x * TL;
+  const rsrc_t rT = make_buf(a.T + vol * a.vol_stride, a.vol_stride * 8);
+  const rsrc_t rtw = make_buf(a.tw, (long long)P * 8);
+
+  // 1. coalesced load of the column tile: thread -> (plane z, column c)
+  for (int i = t; i < TL * P; i += NT) {
+    const int c = i % TL, z = i / TL;
+    const int l = l0 + c;
+    const bool in = z < a.din && l < a.NH;
+    const f2b v = bld2(rT, in ? int(((long long)z * a.plane + (long long)y * a.NHP + l) * 8) : 0x70000000, 0);
+    s_lds[c][z] = v.x;
+    s_lds[c][C::S + z] = v.y;
+  }
+  __syncthreads();
+
+  // 2. one FFT per slot (column c); lane j holds z = P2 * y1 + j, y1 < P1
+  const int c = t / G, j = t % G;
+  float* re = s_lds[c];
+  float* im = s_lds[c] + C::S;
+  cx x[P1];
+  if (j < P2) {
+#pragma unroll
+    for (int y1 = 0; y1 < P1; ++y1) x[y1] = {re[P2 * y1 + j], im[P2 * y1 + j]};
+  }
+  __syncthreads();
+  if (j < P2) {
+    DftSel<P1, SIGN>::run(x);
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) {
+      const f2b w = bld2(rtw, j * 8, k1 * P2 * 8);  // w_P^(k1 j), forward sign
+      x[k1] = SIGN < 0 ? cmul(x[k1], cx{w.x, w.y}) : cmulconj(x[k1], cx{w.x, w.y});
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P1; ++k1) {
+      re[k1 * C::SA + j] = x[k1].x;
+      im[k1 * C::SA + j] = x[k1].y;
+    }
+  }
+  __syncthreads();
+  cx b[P2];
+  if (j < P1) {
+#pragma unroll
+    for (int jj = 0; jj < P2; ++jj) b[jj] = {re[j * C::SA + jj], im[j * C::SA + jj]};
+    DftSel<P2, SIGN>::run(b);
+  }
+  __syncthreads();
+  if (j < P1) {
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) {  // output index k = k1 + P1 k2 with k1 = j
+      re[j + P1 * k2] = b[k2].x;
+      im[j + P1 * k2] = b[k2].y;
+    }
+  }
+  __syncthreads();
+
+  // 3. coalesced store of the first dout planes
+  for (int i = t; i < TL * a.dout; i += NT) {
+    const int cc = i % TL, z = i / TL;
+    const int l = l0 + cc;
+    if (l < a.NH)
+      bst2(rT, s_lds[cc][z], s_lds[cc][C::S + z],
+           int(((long long)z * a.plane + (long long)y * a.NHP + l) * 8), 0);
+  }
+}
+
+template <int P1, int P2>
+struct ZLaunch {
+  using C = ZCfg<P1, P2>;
+  static hipError_t run(const ZfftArgs& a, int sign, int B, hipStream_t s) {
+    const dim3 grid((a.NH + C::TL - 1) / C::TL, a.R, B), blk(C::TL * C::G);
+    if (sign < 0) hipLaunchKernelGGL((k_zfft<P1, P2, -1>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((k_zfft<P1, P2, +1>), grid, blk, 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+#define GFC_Z_ENTRY(p1, p2) ZKernels{p1 * p2, p1, p2, &ZLaunch<p1, p2>::run}
+
+}  // namespace gfc
