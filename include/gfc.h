@@ -82,10 +82,15 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream);
  *   "col_c"     1..64   (power of two) columns per workgroup in the column pass
  *   "col_rows"  16|32   rows per thread in the forward column pass
  *   "col_rows_b" 16|32  rows per thread in the backward column pass
- * The project's autotuner chooses these per (H, W, M, N); host-only.
- * gfc_plan_get_param also reads two fixed values: "low_bins" (K: row frequencies l <= K
- * reach the forward column pass as the x- and y-parts of the divergence separately) and
- * "low_bins_b" (Kb: backward columns l <= Kb take -D_y inside the column recursion).
+ *   "low_bins"  4..32   K: row frequencies l <= K reach the forward column pass as the x-
+ *                       and y-parts of the divergence separately (split form), 2K < N.
+ *                       Changes the rounding, not the exact result: larger K costs a
+ *                       direct-sum pass over the gradient for l in (4, K]. The default is
+ *                       the smallest of 4, 8, 16, 32 with N <= 16 K M (thin, wide tori
+ *                       get more: their solution is dominated by the lowest row bins).
+ * The project's autotuner chooses the launch values per (H, W, M, N); host-only.
+ * gfc_plan_get_param also reads the fixed "low_bins_b" (Kb: backward columns l <= Kb take
+ * -D_y inside the column recursion).
  */
 gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value);
 gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value);

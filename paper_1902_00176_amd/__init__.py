@@ -142,7 +142,7 @@ def _stream_ptr(torch, device, stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-PARAMS = ("row_fppw", "row_ppw", "col_c", "col_rows", "col_rows_b")
+PARAMS = ("row_fppw", "row_ppw", "col_c", "col_rows", "col_rows_b", "low_bins")
 _TUNING_PATH = os.path.join(_HERE, "tuning.json")
 _tuning_db = None
 

@@ -130,7 +130,19 @@ namespace {
 
 
 // launch geometry that follows from the sizes and the tunable parameters
+// Row bins handed to the column pass in split form. The rounding of the row FFT in bins
+// l > K reaches the solution amplified by about N / (K M) (the column frequency 0 carries
+// about 1/M of it, the Green's function 1/lambda_l grows as (N / l)^2, the split form's error
+// shrinks with l): the smallest K in {4, 8, 16, 32} with N <= 16 K M keeps it near 2e-6
+// for float32 input, and only thin, wide tori need more than kLowBins.
+int auto_low_bins(int M, int N) {
+  int K = kLowBins;
+  while (K < kMaxLowBins && (long long)N > 16LL * K * M) K *= 2;
+  return std::min(K, std::max(kLowBins, N / 2 - 1));
+}
+
 void derive_geometry(gfc_plan_s* p) {
+  p->KP = (p->K + 1 + 7) / 8 * 8;
   p->gf = col_geometry(p->H + 1, p->M, p->r0, p->col_rows, p->col_c);
   p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows_b, p->col_c);
   p->nfslots = ((p->H + 2) / 2 + p->row_fppw - 1) / p->row_fppw;
@@ -182,7 +194,7 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
   p->ox = (N - W) / 2;
   p->r0 = M - p->oy;  // grid corner (0,0) relative to the block at the origin
   p->c0 = N - p->ox;
-  p->K = kLowBins;  // the row lengths compiled in all have N / 2 > kLowBins
+  p->K = auto_low_bins(M, N);
   p->Kb = std::min(kLowBinsB, p->NH - 1);
   // row strides padded to whole 256-byte lines so column tiles never straddle cache lines
   p->NHP = (p->NH + 31) / 32 * 32;
@@ -191,7 +203,6 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
     delete p;
     return GFC_E_SIZE;
   }
-  p->KP = (p->K + 1 + 7) / 8 * 8;
   p->KbP = (p->Kb + 1 + 31) / 32 * 32;
   p->flags = flags;
   p->rk = rk;
@@ -229,6 +240,9 @@ gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
   } else if (!std::strcmp(name, "col_rows_b")) {
     if (value != 16 && value != 32) return GFC_E_ARG;
     p->col_rows_b = value;
+  } else if (!std::strcmp(name, "low_bins")) {
+    if (value < kLowBins || value > kMaxLowBins || 2 * value >= p->N) return GFC_E_ARG;
+    p->K = value;
   } else {
     return GFC_E_ARG;
   }
@@ -257,7 +271,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   std::vector<f2> twA(size_t(N1) * N2), twB(size_t(N1) * N2), sxm(NH), dsh(NH);
   // low-bin twiddles of the forward row pass, lane j < N2 of a G-lane slot:
   // [0][l][j] = (1 - w_N^l) w_N^(l j) for Ex, [1][l][j] = w_N^(l j) for Ey (0 for j >= N2)
-  const int G = p->rk->G, K1 = p->K + 1;
+  const int G = p->rk->G, K1 = kLowBins + 1;
   std::vector<f2> twL(size_t(2) * K1 * G, f2{0.f, 0.f});
   for (int l = 0; l < K1; ++l) {
     const double h = std::sin(kPi * double(l) / double(N));
@@ -271,6 +285,19 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
       twL[size_t(l) * G + j] = f2{float(ar * wr - ai * wi), float(ar * wi + ai * wr)};
       twL[size_t(K1 + l) * G + j] = f2{float(wr), float(wi)};
     }
+  }
+  // direct-sum twiddles of the extra split bins: w_N^m for m < N, then 1 - w_N^l
+  std::vector<f2> twX(size_t(N) + kMaxLowBins + 1);
+  for (int m = 0; m < N; ++m) {
+    double c, s;
+    cs2pi(m, N, c, s);
+    twX[m] = f2{float(c), float(-s)};
+  }
+  for (int l = 0; l <= kMaxLowBins; ++l) {
+    const double h = std::sin(kPi * double(l) / double(N));
+    double c, s;
+    cs2pi(l, N, c, s);
+    twX[size_t(N) + l] = f2{float(2.0 * h * h), float(s)};
   }
   for (int k1 = 0; k1 < N1; ++k1)
     for (int j = 0; j < N2; ++j) {
@@ -296,6 +323,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   const size_t o_twA = off; off = align256(off + twA.size() * sizeof(f2));
   const size_t o_twB = off; off = align256(off + twB.size() * sizeof(f2));
   const size_t o_twL = off; off = align256(off + twL.size() * sizeof(f2));
+  const size_t o_twX = off; off = align256(off + twX.size() * sizeof(f2));
   const size_t o_sxm = off; off = align256(off + sxm.size() * sizeof(f2));
   const size_t o_dsh = off; off = align256(off + dsh.size() * sizeof(f2));
   const size_t o_ccf = off; off = align256(off + ccf.size() * sizeof(ColConst));
@@ -304,6 +332,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   std::memcpy(host.data() + o_twA, twA.data(), twA.size() * sizeof(f2));
   std::memcpy(host.data() + o_twB, twB.data(), twB.size() * sizeof(f2));
   std::memcpy(host.data() + o_twL, twL.data(), twL.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twX, twX.data(), twX.size() * sizeof(f2));
   std::memcpy(host.data() + o_sxm, sxm.data(), sxm.size() * sizeof(f2));
   std::memcpy(host.data() + o_dsh, dsh.data(), dsh.size() * sizeof(f2));
   std::memcpy(host.data() + o_ccf, ccf.data(), ccf.size() * sizeof(ColConst));
@@ -322,6 +351,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   p->twA = reinterpret_cast<f2*>(base + o_twA);
   p->twB = reinterpret_cast<f2*>(base + o_twB);
   p->twL = reinterpret_cast<f2*>(base + o_twL);
+  p->twX = reinterpret_cast<f2*>(base + o_twX);
   p->sxm = reinterpret_cast<f2*>(base + o_sxm);
   p->dshift = reinterpret_cast<f2*>(base + o_dsh);
   p->ccf = reinterpret_cast<ColConst*>(base + o_ccf);
@@ -359,7 +389,9 @@ gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
   if (stage == 0 || stage == 1) {
-    const gfc_status st = hip_status(p->rk->fwd(row_fwd_args(p, gx, gy, T, SB), B, s));
+    const RowFwdArgs f = row_fwd_args(p, gx, gy, T, SB);
+    gfc_status st = hip_status(p->rk->fwd(f, B, s));
+    if (st == GFC_OK) st = hip_status(launch_low_ext(f, B, s));
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 2) {
@@ -403,6 +435,10 @@ static gfc_status solve_forward(gfc_plan_t p, const float* gx, const float* gy, 
   f.alpha = alpha;
   gfc_status st = hip_status(p->rk->fwd(f, B, s));
   if (st != GFC_OK) return st;
+  if (edit != kInLaplacian) {
+    st = hip_status(launch_low_ext(f, B, s));
+    if (st != GFC_OK) return st;
+  }
   if (edit == kInLaplacian) {
     st = hip_status(launch_sb_prefix(SB, p->H, p->KP, f.img_sb, B, s));
     if (st != GFC_OK) return st;

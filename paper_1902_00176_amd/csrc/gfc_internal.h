@@ -14,7 +14,10 @@ struct f2 {
 // origin), T1[y, l] = L^[y, l] for l > K, and the split form T1[y, l] = (1 - w_N^l) Ex^[y, l],
 // SB[y, l] = Ey^[y, l] for l <= K (T1[y, 0] = 0). L is formed in float32 from the gradient
 // and two rows of L share one complex FFT; the K + 1 lowest bins of Ex and Ey are direct sums.
-constexpr int kLowBins = 4;  // K: row frequencies l <= K arrive at the column pass split
+constexpr int kLowBins = 4;  // row frequencies l <= 4 are split inside the row pass
+// A plan may split more bins, K in (kLowBins, kMaxLowBins]: the bins l in (kLowBins, K] are
+// then overwritten in split form by launch_low_ext after the row pass (thin, wide images).
+constexpr int kMaxLowBins = 32;
 // On-device gradient edits applied to every loaded pixel before the divergence:
 // threshold (Sec. 3.2.3): E kept where fl(fl(gx^2) + fl(gy^2)) >= tau2, else 0;
 // GDM (eq. (26)): E scaled to |E|^(1-alpha) C^alpha, orientation kept, 0 where E = 0.
@@ -31,8 +34,10 @@ struct RowFwdArgs {
   f2* T1;             // [B][H+1][NHP]  (NHP = NH rounded up to 32: row stride)
   f2* SB;             // [B][H][KP]     (KP = side-array row stride >= K + 1)
   const f2* twA;      // [N1][N2]: w_N^(k1 j), forward sign
-  const f2* twL;      // [2][K+1][G]: (1 - w_N^l) w_N^(l j) and w_N^(l j), 0 for j >= N2
+  const f2* twL;      // [2][kLowBins+1][G]: (1 - w_N^l) w_N^(l j) and w_N^(l j), 0 for j >= N2
+  const f2* twX;      // [N + kMaxLowBins + 1]: w_N^m (m < N), then 1 - w_N^l (l <= kMaxLowBins)
   int H, W, K, KP;
+  int N, NHP;         // row length and T1 row stride (used by launch_low_ext)
   int ppw;            // pairs of L rows per slot
   int npairs;         // ceil((H+1) / 2)
   long long img_in, img_t1, img_sb;
@@ -62,6 +67,9 @@ struct RowInvArgs {
 
 // Laplacian input: SB[y][0] <- sum_{y' <= y} SB[y'][0] for y in [0, H) of every image, so the
 // column pass's split form (1 - S) b reproduces the DC column of L (float64 running sums).
+// Bins kLowBins < l <= K of T1 and SB in the split form, as direct float32 sums over the
+// (edited) gradient rows; run after the row pass on the same stream. No-op for K <= kLowBins.
+hipError_t launch_low_ext(const RowFwdArgs& a, int B, hipStream_t s);
 hipError_t launch_sb_prefix(f2* SB, int H, int KP, long long img_sb, int B, hipStream_t s);
 
 // Colour correction of eq. (25) in place on u [B][npix]: every workgroup of image b reduces
@@ -229,5 +237,8 @@ hipError_t launch_col_fwd_rg(const RgBase& base, const RgCol* tab, const RgItem*
                              int nlow, const RgItem* rest, int nrest, int Lseg, bool tail,
                              int threads, size_t shm, hipStream_t s);
 constexpr int kColMaxThreads = 1024;  // largest column-pass workgroup
+// ragged low-bin extension: items (image, row y <= H) of the images whose plan has K > kLowBins
+hipError_t launch_low_ext_rg(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+                             int nitems, hipStream_t s);
 
 }  // namespace gfc

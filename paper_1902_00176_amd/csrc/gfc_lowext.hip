@@ -1,0 +1,154 @@
+// gfc_lowext.hip - more row bins in split form for thin, wide images.
+//
+// The column pass amplifies a rounding error in row bin l of the divergence spectrum by up
+// to 1/lambda_l ~ (N / (2 pi l))^2 at column frequency 0 (Sec. 3, eq. (23)). The row pass
+// therefore hands the lowest bins l <= kLowBins over in the split form (1 - w_N^l) Ex^ and
+// Ey^, whose rounding is not amplified that way. When the torus has few rows (M small) the
+// column frequency 0 carries a large share of the solution and the bins just above
+// kLowBins still cost precision, so such plans split up to K bins: this kernel overwrites
+// T1[y, l] and SB[y, l] for kLowBins < l <= K with the split values
+//   T1[y, l] = (1 - w_N^l) sum_x Ex[y, x] w_N^(l x)   (y <= H; row H of Ex is 0)
+//   SB[y, l] = sum_x Ey[y, x] w_N^(l x)               (y < H)
+// as float32 direct sums. Workgroup: one row y, kExtWaves wavefronts of kExtBins bins each;
+// lane j takes x = j, j + 64, ... and the 64 lane sums are added through LDS.
+#include <hip/hip_runtime.h>
+
+#include "gfc_edit.h"
+#include "gfc_internal.h"
+
+namespace gfc {
+namespace {
+
+constexpr int kExtBins = 4;   // bins per wavefront
+constexpr int kExtWaves = 4;  // wavefronts per workgroup
+constexpr int kExtVals = 4 * kExtBins;  // floats per lane: (Ex, Ey) x (re, im) per bin
+
+struct cxf {
+  float x, y;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One row y of one image; grp selects kExtWaves * kExtBins consecutive bins.
+template <int EDIT>
+__device__ __forceinline__ void low_ext_row(const RowFwdArgs& p, int y, int grp) {
+  __shared__ float s_sum[kExtWaves][kExtVals][65];
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  const int lb = kLowBins + 1 + (grp * kExtWaves + wave) * kExtBins;  // first bin of the wave
+  if (lb > p.K) return;  // the waves of a workgroup never wait for each other
+  cxf ax[kExtBins], ay[kExtBins];
+  int m[kExtBins], d[kExtBins];
+#pragma unroll
+  for (int i = 0; i < kExtBins; ++i) {
+    const int l = lb + i;
+    ax[i] = ay[i] = {0.f, 0.f};
+    m[i] = (l * lane) % p.N;  // exponent l x mod N for x = lane
+    d[i] = (l * 64) % p.N;    // its step from x to x + 64
+  }
+  if (y < p.H) {
+    const float* gx = p.gx + (long long)y * p.W;
+    const float* gy = p.gy + (long long)y * p.W;
+    const float* gc = EDIT == kEditGdm ? p.C + (long long)y * p.W : nullptr;
+    for (int x = lane; x < p.W; x += 64) {
+      float vx = gx[x], vy = gy[x];
+      if constexpr (EDIT != kEditNone)
+        edit_pixel<EDIT>(vx, vy, EDIT == kEditGdm ? gc[x] : 0.f, p.tau2, p.alpha);
+#pragma unroll
+      for (int i = 0; i < kExtBins; ++i) {
+        const f2 w = p.twX[m[i]];
+        ax[i].x = __builtin_fmaf(vx, w.x, ax[i].x);
+        ax[i].y = __builtin_fmaf(vx, w.y, ax[i].y);
+        ay[i].x = __builtin_fmaf(vy, w.x, ay[i].x);
+        ay[i].y = __builtin_fmaf(vy, w.y, ay[i].y);
+        m[i] += d[i];
+        if (m[i] >= p.N) m[i] -= p.N;
+      }
+    }
+  }
+  // Ex bins times 1 - w_N^l (float64-built), then the sums over the lanes
+  float* s = &s_sum[wave][0][0];
+#pragma unroll
+  for (int i = 0; i < kExtBins; ++i) {
+    const int l = lb + i <= kMaxLowBins ? lb + i : 0;
+    const f2 o = p.twX[p.N + l];
+    s[(4 * i + 0) * 65 + lane] = ax[i].x * o.x - ax[i].y * o.y;
+    s[(4 * i + 1) * 65 + lane] = ax[i].x * o.y + ax[i].y * o.x;
+    s[(4 * i + 2) * 65 + lane] = ay[i].x;
+    s[(4 * i + 3) * 65 + lane] = ay[i].y;
+  }
+  wave_sync();
+  if (lane < kExtVals) {
+    float sum = 0.f;
+    for (int j = 0; j < 64; ++j) sum += s[lane * 65 + j];
+    const int i = lane / 4, comp = lane & 1;
+    const int l = lb + i;
+    if (l <= p.K) {
+      float* t1 = reinterpret_cast<float*>(p.T1);
+      float* sb = reinterpret_cast<float*>(p.SB);
+      if ((lane & 2) == 0)
+        t1[2 * ((long long)y * p.NHP + l) + comp] = sum;
+      else if (y < p.H)
+        sb[2 * ((long long)y * p.KP + l) + comp] = sum;
+    }
+  }
+}
+
+template <int EDIT>
+__global__ void __launch_bounds__(64 * kExtWaves) k_low_ext(RowFwdArgs p) {
+  const long long b = blockIdx.z;
+  p.gx += b * p.img_in;
+  p.gy += b * p.img_in;
+  if (EDIT == kEditGdm) p.C += b * p.img_in;
+  p.T1 += b * p.img_t1;
+  p.SB += b * p.img_sb;
+  low_ext_row<EDIT>(p, int(blockIdx.x), int(blockIdx.y));
+}
+
+__global__ void __launch_bounds__(64 * kExtWaves)
+k_low_ext_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
+  const RgItem it = items[blockIdx.x];
+  const RgRowFwd& e = tab[it.img];
+  RowFwdArgs p = e.a;
+  p.gx = base.gx + e.in;
+  p.gy = base.gy + e.in;
+  p.T1 = reinterpret_cast<f2*>(base.ws + e.t);
+  p.SB = reinterpret_cast<f2*>(base.ws + e.side);
+  low_ext_row<kEditNone>(p, it.blk, int(blockIdx.y));
+}
+
+constexpr int kBinsPerGroup = kExtWaves * kExtBins;
+constexpr int kMaxGroups = (kMaxLowBins - kLowBins + kBinsPerGroup - 1) / kBinsPerGroup;
+
+}  // namespace
+
+hipError_t launch_low_ext(const RowFwdArgs& a, int B, hipStream_t s) {
+  if (a.K <= kLowBins || B <= 0) return hipSuccess;
+  if (a.K > kMaxLowBins || 2 * a.K >= a.N || !a.twX || !a.gx || !a.gy ||
+      (a.edit == kEditGdm && !a.C) || B > 65535)
+    return hipErrorInvalidValue;
+  const dim3 grid(unsigned(a.H + 1), unsigned((a.K - kLowBins + kBinsPerGroup - 1) / kBinsPerGroup),
+                  unsigned(B));
+  const dim3 block(64 * kExtWaves);
+  switch (a.edit) {
+    case kEditNone: k_low_ext<kEditNone><<<grid, block, 0, s>>>(a); break;
+    case kEditThreshold: k_low_ext<kEditThreshold><<<grid, block, 0, s>>>(a); break;
+    case kEditGdm: k_low_ext<kEditGdm><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_low_ext_rg(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+                             int nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  // every image of the list has K <= kMaxLowBins; groups past an image's K return at once
+  k_low_ext_rg<<<dim3(unsigned(nitems), unsigned(kMaxGroups)), dim3(64 * kExtWaves), 0, s>>>(
+      base, tab, items);
+  return hipGetLastError();
+}
+
+}  // namespace gfc

@@ -39,7 +39,8 @@ struct gfc_plan_s {
   bool built = false;
   int device = -1;
   void* dmem = nullptr;
-  gfc::f2 *twA = nullptr, *twB = nullptr, *twL = nullptr, *sxm = nullptr, *dshift = nullptr;
+  gfc::f2 *twA = nullptr, *twB = nullptr, *twL = nullptr, *twX = nullptr, *sxm = nullptr,
+          *dshift = nullptr;
   gfc::ColConst *ccf = nullptr, *ccb = nullptr;
   // a side stream for the forward column pass's low tiles, joined back with two events
   hipStream_t side = nullptr;
@@ -89,10 +90,13 @@ inline RowFwdArgs row_fwd_args(const gfc_plan_s* p, const float* gx, const float
   a.SB = SB;
   a.twA = p->twA;
   a.twL = p->twL;
+  a.twX = p->twX;
   a.H = p->H;
   a.W = p->W;
   a.K = p->K;
   a.KP = p->KP;
+  a.N = p->N;
+  a.NHP = p->NHP;
   a.ppw = p->row_fppw;
   a.npairs = (p->H + 2) / 2;
   a.img_in = (long long)p->H * p->W;

@@ -4,6 +4,7 @@
 // with the same sizes share one). The three passes run over all images at once:
 //   row pass      one launch per distinct row length N (the FFT code is specialised on N),
 //                 spread over four streams, each workgroup one (image, strip block) item;
+//                 then one launch of the extra split row bins of thin images (K > 4);
 //   column pass   one launch for the tiles holding columns l <= K and one for the rest,
 //                 covering every image, each workgroup one (image, column tile) item;
 //   inverse row   as the row pass.
@@ -63,6 +64,7 @@ struct gfc_ragged_s {
     bool half;  // every image of the group has 2 W <= N
   };
   std::vector<Group> groups;  // one per distinct N
+  int x_off = 0, x_n = 0;  // low-bin extension items (image, row) of images with K > kLowBins
   int c_low_off = 0, c_low_n = 0, c_rest_off = 0, c_rest_n = 0;
   int c_threads = 64;
   size_t c_shm = 0;
@@ -114,6 +116,8 @@ gfc_status enqueue(gfc_ragged_s* r, const RgBase& base, hipStream_t main) {
       return GFC_E_HIP;
   }
   if (!join(kRgStreams)) return GFC_E_HIP;
+  if (launch_low_ext_rg(base, r->tab_f, r->items + r->x_off, r->x_n, main) != hipSuccess)
+    return GFC_E_HIP;
   if (launch_col_fwd_rg(base, r->tab_c, r->items + r->c_low_off, r->c_low_n,
                         r->items + r->c_rest_off, r->c_rest_n, kRgColRows, r->c_tail,
                         r->c_threads, r->c_shm, main) != hipSuccess)
@@ -269,6 +273,13 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
     g.i_n = int(items.size()) - g.i_off;
     r->groups.push_back(g);
   }
+  r->x_off = int(items.size());
+  for (int i : order) {
+    const gfc_plan_s* p = r->plans[r->plan_of[i]];
+    if (p->K > kLowBins)
+      for (int y = 0; y <= p->H; ++y) items.push_back(RgItem{i, y});
+  }
+  r->x_n = int(items.size()) - r->x_off;
   int threads = 64;
   size_t shm = 0;
   bool tail = false;

@@ -12,6 +12,7 @@
 #pragma once
 #include "gfc_buf.h"
 #include "gfc_dft.h"
+#include "gfc_edit.h"
 #include "gfc_internal.h"
 
 #include <utility>
@@ -226,24 +227,6 @@ __device__ __forceinline__ void pair_block(cx (&a)[N1], cx (&ax0)[kLowBins],
   a[Y1] = {(gx0 - gx0m) + (gy0 - gym), (gx1 - gx1m) + (gy1 - gy0)};
   low_acc<N1, Y1>(ax0, ay0, gx0, gy0, std::make_integer_sequence<int, kLowBins>{});
   low_acc<N1, Y1>(ax1, ay1, gx1, gy1, std::make_integer_sequence<int, kLowBins>{});
-}
-
-// Gradient edits of one pixel (before the divergence). Threshold: the decision uses the
-// same float32 rounding sequence as its specification (no contraction). GDM: the weighted
-// geometric mean of eq. (26) through log2/exp2 in float32.
-template <int EDIT>
-__device__ __forceinline__ void edit_pixel(float& gx, float& gy, float c, float tau2,
-                                           float alpha) {
-  if constexpr (EDIT == kEditThreshold) {
-    const float m = __fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy));
-    if (!(m >= tau2)) gx = gy = 0.f;
-  } else if constexpr (EDIT == kEditGdm) {
-    const float m = gx * gx + gy * gy;
-    const float lc = alpha > 0.f ? alpha * log2f(c) : 0.f;  // C^alpha, with C^0 = 1
-    const float sc = m > 0.f ? exp2f(lc - 0.5f * alpha * log2f(m)) : 0.f;
-    gx *= sc;
-    gy *= sc;
-  }
 }
 
 // Edited variant of one y1 block: both components (and C) at the five pixels the divergence
@@ -586,7 +569,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
           const cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
           bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
           if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
-          if (EDIT == kInLaplacian && l <= KL) {
+          if (EDIT == kInLaplacian && l <= p.K) {
             const bool dc = l == 0;
             if (y0 < p.H) bst2(rSB, dc ? A.x : 0.f, dc ? A.y : 0.f, (y0 * p.KP + l) * 8, 0);
             if (y0 + 1 < p.H) bst2(rSB, dc ? B.x : 0.f, dc ? B.y : 0.f, ((y0 + 1) * p.KP + l) * 8, 0);

@@ -113,19 +113,28 @@ def test_ragged_create_host_logic():
     L.gfc_ragged_destroy(h)
 
 
-def test_plan_parameters_round_trip_and_fixed_low_bins():
+def test_plan_parameters_round_trip_and_low_bins():
     """Launch parameters are set and read back on the host; out-of-range values and unknown
-    names are rejected; K and Kb are read-only values of the plan."""
-    want = {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32, "col_rows_b": 16}
+    names are rejected; Kb is a read-only value of the plan; K defaults by the torus shape
+    (the smallest of 4, 8, 16, 32 with N <= 16 K M) and may be raised up to 32."""
+    want = {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32, "col_rows_b": 16,
+            "low_bins": 4}
     p = gfc.Plan(801, 1200, params=want, tuned=False)
     assert p.params == want
-    assert p.get_param("low_bins") == 4
     assert p.get_param("low_bins_b") == 64
     L = gfc.lib()
     for name, value in (("row_fppw", 0), ("row_fppw", 65), ("col_c", 3), ("col_rows", 24),
-                        ("col_rows_b", 8),
-                        ("low_bins", 8), ("row_strip", 4)):
+                        ("col_rows_b", 8), ("low_bins", 3), ("low_bins", 33),
+                        ("low_bins_b", 8), ("row_strip", 4)):
         assert L.gfc_plan_set_param(p.handle, name.encode(), value) == 1, (name, value)
-    # a short row: Kb is capped by the half spectrum
+    assert L.gfc_plan_set_param(p.handle, b"low_bins", 13) == 0
+    assert p.get_param("low_bins") == 13
+    # a short row: Kb is capped by the half spectrum; K may not reach N / 2
     q = gfc.Plan(5, 6, 12, 16)
     assert q.get_param("low_bins") == 4 and q.get_param("low_bins_b") == 8
+    assert L.gfc_plan_set_param(q.handle, b"low_bins", 8) == 1
+    # default K by the torus shape: N <= 16 K M
+    for (H, W, M, N), K in (((2, 1200, 6, 2400), 32), ((8, 1200, 16, 2400), 16),
+                            ((16, 1200, 32, 2400), 8), ((32, 1200, 64, 2400), 4),
+                            ((3, 1250, 8, 2400), 32), ((5000, 6, 10000, 16), 4)):
+        assert gfc.Plan(H, W, M, N, tuned=False).get_param("low_bins") == K, (H, W, M, N)

@@ -51,7 +51,7 @@ def _edge_map(seed, B, H, W):
 
 SHAPES = [  # H, W, M, N: narrow slots, odd sizes, minimal padding (every column block), 2400
     (64, 64, 128, 128), (31, 45, 64, 96), (100, 37, 210, 80), (33, 70, 35, 72),
-    (801, 1200, 1620, 2400),
+    (801, 1200, 1620, 2400), (4, 1200, 10, 2400),  # thin and wide: 16 row bins split
 ]
 
 

@@ -98,3 +98,16 @@ def test_laplacian_entry_agrees_with_gradient_entry():
     u_g = gfc.solve(torch.from_numpy(gx32).cuda(), torch.from_numpy(gy32).cuda(), M, N).cpu().numpy()
     for i in range(2):
         assert np.linalg.norm(u_l[i] - u_g[i]) / np.linalg.norm(u_g[i]) <= TOL
+
+
+def test_laplacian_solve_with_more_split_bins():
+    """A plan that splits more row bins (K = 16): a given divergence has no x/y split, so the
+    bins (4, K] keep the FFT values and their side entries must be zero."""
+    H, W, M, N = 64, 64, 128, 128
+    gx, gy = _fields(3470, 2, H, W)
+    L = _support_div(gx, gy).astype(np.float32)
+    p = gfc.Plan(H, W, M, N, params={"low_bins": 16}, tuned=False)
+    u = p.solve_laplacian(torch.from_numpy(L).cuda()).cpu().numpy()
+    for i in range(2):
+        ref = O.solve_laplacian(L[i], M, N)
+        assert np.linalg.norm(u[i] - ref) / np.linalg.norm(ref) <= TOL

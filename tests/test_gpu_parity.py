@@ -80,6 +80,11 @@ SHAPES = [
     (33, 70, 35, 72),      # minimal padding in both directions (M = H + 2, N = W + 2)
     (129, 200, 260, 400),
     (255, 300, 513, 640),
+    (3, 1250, 8, 2400),    # 2W > N on the longest rows: every element column is loaded
+    (2, 1200, 6, 2400),    # the widest default row (one FFT slot per wavefront), K = 32
+    (8, 1200, 16, 2400),   # thin and wide: 16 row bins split
+    (16, 1200, 32, 2400),  # 8 row bins split
+    (5000, 6, 10000, 16),  # a tall column: over 300 row segments in one workgroup
 ]
 
 
@@ -91,6 +96,25 @@ def test_forward_parity_small_shapes(H, W, M, N):
     ref = O.solve_fft(gx, gy, M, N)
     errs = per_image_rel(u, ref)
     assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("K", [5, 16, 32])
+def test_forward_more_split_bins(K):
+    """Raising K moves the row bins (4, K] from the FFT to the split form of the extension
+    pass: the exact result is the same, so the oracle bar holds for every K."""
+    H, W, M, N = 40, 300, 84, 640
+    _say(f"forward parity with low_bins={K} H={H} W={W} M={M} N={N}")
+    gx, gy = _rand_fields(777 + K, 3, H, W)
+    p = gfc.Plan(H, W, M, N, params={"low_bins": K}, tuned=False)
+    assert p.get_param("low_bins") == K
+    tx = torch.from_numpy(gx).cuda()
+    ty = torch.from_numpy(gy).cuda()
+    u = p.solve(tx, ty).cpu().numpy()
+    errs = per_image_rel(u, O.solve_fft(gx, gy, M, N))
+    assert max(errs) <= TOL, errs
+    # and agrees with the default split to float32 rounding
+    u4 = gfc.Plan(H, W, M, N, params={"low_bins": 4}, tuned=False).solve(tx, ty).cpu().numpy()
+    assert max(per_image_rel(u, u4)) <= TOL
 
 
 def test_forward_small64_workload():
@@ -182,7 +206,8 @@ def test_nonfinite_input_propagates():
 # ---------------------------------------------------------------- backward
 
 @pytest.mark.parametrize("H,W,M,N", [(64, 64, 128, 128), (31, 45, 64, 96), (100, 37, 210, 80),
-                                     (1, 37, 3, 80), (33, 70, 35, 72), (129, 200, 260, 400)])
+                                     (1, 37, 3, 80), (33, 70, 35, 72), (129, 200, 260, 400),
+                                     (2, 1200, 6, 2400), (5000, 6, 10000, 16)])
 def test_backward_parity(H, W, M, N):
     _say(f"backward parity H={H} W={W} M={M} N={N}")
     rng = np.random.default_rng(H + 3 * W)

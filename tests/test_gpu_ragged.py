@@ -49,8 +49,10 @@ def _fields(sizes, seed):
 
 # mixed sizes: tiny, odd, one image taller than its torus allows for widened segments (tail),
 # repeated sizes (shared plan), low and high row lengths
+# and thin, wide images whose plans split more row bins (K = 32 and 16)
 MIXED = [(64, 64, 0, 0), (37, 45, 0, 0), (1, 37, 3, 80), (33, 70, 35, 72), (64, 64, 0, 0),
-         (129, 200, 260, 400), (5, 3, 16, 16), (255, 300, 513, 640), (100, 37, 210, 80)]
+         (129, 200, 260, 400), (5, 3, 16, 16), (255, 300, 513, 640), (100, 37, 210, 80),
+         (3, 1250, 8, 2400), (2, 300, 0, 0)]
 
 
 def _run_mixed(flags=0):
