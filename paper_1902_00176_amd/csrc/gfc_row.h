@@ -184,6 +184,20 @@ __device__ __forceinline__ void low_acc(cx (&ax)[kLowBins], cx (&ay)[kLowBins + 
 // together.
 constexpr int kOOB = 0x70000000;  // a byte offset past every image (plans keep them < 2^30)
 
+// One slot per wavefront: the element x - 1 of lane j is lane j - 1's element x (a DPP
+// shift of the whole wavefront by one lane); lane 0 takes `carry`, the previous y1 block's
+// element of lane N2 - 1. Saves the x - 1 loads of the divergence.
+__device__ __forceinline__ float lane_shift(float v, float carry) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, carry),
+                                                               __builtin_bit_cast(int, v),
+                                                               0x138 /* wave_shr:1 */, 0xf,
+                                                               0xf, false));
+}
+template <int N2>
+__device__ __forceinline__ float lane_last(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), N2 - 1));
+}
+
 // One slot per wavefront: the rows are uniform, each row gets its own descriptor whose
 // range is that row (empty outside the image), and x >= W falls outside it.
 struct PairRowsU {
@@ -193,11 +207,14 @@ struct PairRowsU {
 template <int N1, int N2, int Y1>
 __device__ __forceinline__ void pair_block(cx (&a)[N1], cx (&ax0)[kLowBins],
                                            cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
-                                           cx (&ay1)[kLowBins + 1], const PairRowsU& r, int W) {
+                                           cx (&ay1)[kLowBins + 1], const PairRowsU& r, int W,
+                                           float (&cy)[2]) {
   const int v = r.vb + N2 * Y1 * 4;
-  const float gx0 = bld1(r.x0, v, 0), gx0m = bld1(r.x0, v - 4, 0);
-  const float gx1 = bld1(r.x1, v, 0), gx1m = bld1(r.x1, v - 4, 0);
+  const float gx0 = bld1(r.x0, v, 0), gx1 = bld1(r.x1, v, 0);
   const float gym = bld1(r.ym, v, 0), gy0 = bld1(r.y0, v, 0), gy1 = bld1(r.y1, v, 0);
+  const float gx0m = lane_shift(gx0, cy[0]), gx1m = lane_shift(gx1, cy[1]);
+  cy[0] = lane_last<N2>(gx0);
+  cy[1] = lane_last<N2>(gx1);
   a[Y1] = {(gx0 - gx0m) + (gy0 - gym), (gx1 - gx1m) + (gy1 - gy0)};
   low_acc<N1, Y1>(ax0, ay0, gx0, gy0, std::make_integer_sequence<int, kLowBins>{});
   low_acc<N1, Y1>(ax1, ay1, gx1, gy1, std::make_integer_sequence<int, kLowBins>{});
@@ -214,7 +231,8 @@ struct PairRowsL {
 template <int N1, int N2, int Y1>
 __device__ __forceinline__ void pair_block(cx (&a)[N1], cx (&ax0)[kLowBins],
                                            cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
-                                           cx (&ay1)[kLowBins + 1], const PairRowsL& r, int W) {
+                                           cx (&ay1)[kLowBins + 1], const PairRowsL& r, int W,
+                                           float (&)[2]) {
   const int lim = W - N2 * Y1;  // x < W  <=>  lane < lim
   const bool xin = r.lane < lim, xmin = r.lane <= lim;
   constexpr int so = N2 * Y1 * 4, som = Y1 == 0 ? 0 : N2 * Y1 * 4 - 4;
@@ -240,7 +258,7 @@ template <int N1, int N2, int Y1, int EDIT>
 __device__ __forceinline__ void pair_block_edit(cx (&a)[N1], cx (&ax0)[kLowBins],
                                                 cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
                                                 cx (&ay1)[kLowBins + 1], const EditRowsU& r,
-                                                int W, float tau2, float alpha) {
+                                                int W, float tau2, float alpha, float (&cy)[2]) {
   const int v = r.vb + N2 * Y1 * 4;
   auto px = [&](int row, int off, float& ex, float& ey) {
     ex = bld1(r.x[row], off, 0);
@@ -248,12 +266,16 @@ __device__ __forceinline__ void pair_block_edit(cx (&a)[N1], cx (&ax0)[kLowBins]
     const float c = EDIT == kEditGdm ? bld1(r.c[row], off, 0) : 0.f;
     edit_pixel<EDIT>(ex, ey, c, tau2, alpha);
   };
-  float x0, y0, x0m, y0m, x1, y1, x1m, y1m, xm, ym;
+  float x0, y0, x1, y1, xm, ym, x0m, x1m;
   px(1, v, x0, y0);
-  px(1, v - 4, x0m, y0m);
   px(2, v, x1, y1);
-  px(2, v - 4, x1m, y1m);
   px(0, v, xm, ym);
+  // the edited x - 1 neighbours are the neighbouring lanes' edited values (saves the loads
+  // and the edit of two pixels)
+  x0m = lane_shift(x0, cy[0]);
+  x1m = lane_shift(x1, cy[1]);
+  cy[0] = lane_last<N2>(x0);
+  cy[1] = lane_last<N2>(x1);
   a[Y1] = {(x0 - x0m) + (y0 - ym), (x1 - x1m) + (y1 - y0)};
   low_acc<N1, Y1>(ax0, ay0, x0, y0, std::make_integer_sequence<int, kLowBins>{});
   low_acc<N1, Y1>(ax1, ay1, x1, y1, std::make_integer_sequence<int, kLowBins>{});
@@ -270,7 +292,7 @@ template <int N1, int N2, int Y1, int EDIT>
 __device__ __forceinline__ void pair_block_edit(cx (&a)[N1], cx (&ax0)[kLowBins],
                                                 cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
                                                 cx (&ay1)[kLowBins + 1], const EditRowsL& r,
-                                                int W, float tau2, float alpha) {
+                                                int W, float tau2, float alpha, float (&)[2]) {
   const int lim = W - N2 * Y1;
   const bool xin = r.lane < lim, xmin = r.lane <= lim;
   constexpr int so = N2 * Y1 * 4, som = Y1 == 0 ? 0 : N2 * Y1 * 4 - 4;
@@ -377,17 +399,17 @@ template <int N1, int N2, int NB, int Y1, int EDIT = kEditNone, class Rows>
 __device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
                                           cx (&ay0)[kLowBins + 1], cx (&ax1)[kLowBins],
                                           cx (&ay1)[kLowBins + 1], const Rows& r, int W,
-                                          float tau2 = 0.f, float alpha = 0.f) {
+                                          float (&cy)[2], float tau2 = 0.f, float alpha = 0.f) {
   if constexpr (Y1 < N1) {
     if constexpr (Y1 < NB) {
       if constexpr (EDIT == kEditNone)
-        pair_block<N1, N2, Y1>(a, ax0, ay0, ax1, ay1, r, W);
+        pair_block<N1, N2, Y1>(a, ax0, ay0, ax1, ay1, r, W, cy);
       else
-        pair_block_edit<N1, N2, Y1, EDIT>(a, ax0, ay0, ax1, ay1, r, W, tau2, alpha);
+        pair_block_edit<N1, N2, Y1, EDIT>(a, ax0, ay0, ax1, ay1, r, W, tau2, alpha, cy);
     } else {
       a[Y1] = {0.f, 0.f};
     }
-    pair_load<N1, N2, NB, Y1 + 1, EDIT>(a, ax0, ay0, ax1, ay1, r, W, tau2, alpha);
+    pair_load<N1, N2, NB, Y1 + 1, EDIT>(a, ax0, ay0, ax1, ay1, r, W, cy, tau2, alpha);
   }
 }
 
@@ -432,6 +454,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
     for (int l = 0; l < KL; ++l) ax0[l] = ax1[l] = {0.f, 0.f};
 #pragma unroll
     for (int l = 0; l <= KL; ++l) ay0[l] = ay1[l] = {0.f, 0.f};
+    float cy[2] = {0.f, 0.f};  // x - 1 of the first y1 block: outside the image
     auto row = [&](const float* img, int y) {
       const bool in = ok && y >= 0 && y < p.H;
       return make_buf(img + (in ? (long long)y * p.W : 0), in ? (long long)p.W * 4 : 0);
@@ -490,23 +513,23 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
                            {row(gyi, y0 - 1), row(gyi, y0), row(gyi, y0 + 1)},
                            {row(ci, y0 - 1), row(ci, y0), row(ci, y0 + 1)},
                            (lane < N2 ? lane * 4 : kOOB) + tz};
-      pair_load<N1, N2, NB, 0, EDIT>(a, ax0, ay0, ax1, ay1, rows, p.W, p.tau2, p.alpha);
+      pair_load<N1, N2, NB, 0, EDIT>(a, ax0, ay0, ax1, ay1, rows, p.W, cy, p.tau2, p.alpha);
     } else if constexpr (EDIT != kEditNone) {
       const float* ci = EDIT == kEditGdm ? p.C + b * p.img_in : gxi;
       const int z0 = off(y0), z1 = off(y0 + 1);
       const EditRowsL rows{rgx, rgy, make_buf(ci, p.img_in * 4), {off(y0 - 1), z0, z1},
                            lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
-      pair_load<N1, N2, NB, 0, EDIT>(a, ax0, ay0, ax1, ay1, rows, p.W + tz, p.tau2, p.alpha);
+      pair_load<N1, N2, NB, 0, EDIT>(a, ax0, ay0, ax1, ay1, rows, p.W + tz, cy, p.tau2, p.alpha);
     } else if constexpr (SLOTS == 1) {
       // tz: the per-y1 offsets are formed in the loop, not hoisted and held live
       const PairRowsU rows{row(gxi, y0), row(gxi, y0 + 1), row(gyi, y0 - 1), row(gyi, y0),
                            row(gyi, y0 + 1), (lane < N2 ? lane * 4 : kOOB) + tz};
-      pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W);
+      pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W, cy);
     } else {
       const int z0 = off(y0), z1 = off(y0 + 1);
       const PairRowsL rows{rgx, rgy, off(y0 - 1), z0, z1,
                            lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
-      pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W + tz);  // tz: masks per row pair
+      pair_load<N1, N2, NB, 0>(a, ax0, ay0, ax1, ay1, rows, p.W + tz, cy);  // tz: masks per row pair
     }
 
     // lane factors w_N^(l j) (Ex also times 1 - w_N^l), then the sums over the lanes
@@ -602,9 +625,19 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) 
   }
 }
 
+// Edited loaders hold more values than the plain one; left alone the compiler gives them
+// one wavefront per SIMD. With one slot per workgroup (the x - 1 neighbours come by lane
+// shifts) two wavefronts (a few spilled registers) measured 1.2-1.6x faster; the
+// full-support variants (2 W > N) and the several-slot loaders would spill far more and
+// keep the default.
+template <int N1, int SLOTS, int NB, int EDIT>
+constexpr int kFwdWaves =
+    ((EDIT == kEditThreshold || EDIT == kEditGdm) && NB < N1 && SLOTS == 1) ? 2 : 1;
+
 // NB: y1 blocks that can hold the support [0, W] (all N1, or N1/2 + 1 when 2 W <= N)
 template <int N1, int N2, int SLOTS, int NB, int EDIT>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
+__attribute__((amdgpu_waves_per_eu(kFwdWaves<N1, SLOTS, NB, EDIT>)))
 k_row_fwd(RowFwdArgs p) {
   int bx, by;
   xcd_contiguous(bx, by);
