@@ -202,6 +202,44 @@ def volume_bench(torch, gfc, dev, stream, reps, D=128, B=4):
             "bytes_per_volume": bytes_vol}
 
 
+def small_configs_bench(torch, gfc, dev, stream, reps):
+    """The two smaller batch shapes: 96 solves of 512x512 on 1024x1024 (3 channels of 32
+    merged pairs), forward; and 48 solves of 256x256 on 512x512 (16 x 3 channels, a
+    differentiable layer), forward plus backward. Random float32 gradients of that shape
+    (the timing does not depend on the values)."""
+    out = {}
+    for name, B, H, M, bwd in (("merge512_b96", 96, 512, 1024, False),
+                               ("layer256_b48", 48, 256, 512, True)):
+        plan = gfc.Plan(H, H, M, M).build(dev)
+        gx = torch.randn((B, H, H), device=dev) * 0.1
+        gy = torch.randn((B, H, H), device=dev) * 0.1
+        u = torch.empty_like(gx)
+        ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device=dev)
+
+        def step():
+            plan.solve(gx, gy, out=u, workspace=ws)
+            if bwd:
+                plan.backward(u, workspace=ws)
+
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            step()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        NH = M // 2 + 1
+        per = 12.0 * H * H + 4 * 8.0 * (H + 1) * NH  # plain-path bytes per solve (one way)
+        key = "pairs_per_s" if bwd else "solves_per_s"
+        out[name] = {"torus": [M, M], "batch": B, key: B / (ms / 1e3), "ms_per_step": ms,
+                     "hbm_frac": per * (2 if bwd else 1) * B / (ms / 1e3) / HBM_PEAK}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +251,7 @@ def main():
     ap.add_argument("--no-edit", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--batch", type=int, default=100)
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two counter runs of --pmc-pass")
@@ -435,6 +474,9 @@ def main():
 
     if not args.no_ragged:
         result["ragged"] = ragged_bench(torch, gfc, synth, dev, stream, max(args.steps // 2, 3))
+
+    if not args.no_small:
+        result["small_configs"] = small_configs_bench(torch, gfc, dev, stream, max(args.steps, 5))
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w)
