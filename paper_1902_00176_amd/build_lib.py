@@ -82,6 +82,26 @@ def _lengths_from_env():
     return sorted({int(t) for t in v.replace(",", " ").split()})
 
 
+RGM_BUCKET = 12  # row lengths per multi-length ragged launch
+
+
+def rg_buckets(lengths):
+    """Groups of row lengths that share one ragged launch: lengths of one workgroup size
+    (64 threads for 64-lane slots, else 256), in order, split into near-equal groups of at
+    most RGM_BUCKET."""
+    cls = {}
+    for n in lengths:
+        n1, n2 = choose_factors(n)
+        cls.setdefault(64 if _pow2ceil(max(n1, n2)) == 64 else 256, []).append(n)
+    out = []
+    for t in sorted(cls):
+        ns = sorted(cls[t])
+        k = -(-len(ns) // RGM_BUCKET)
+        size = -(-len(ns) // k)
+        out += [ns[i:i + size] for i in range(0, len(ns), size)]
+    return out
+
+
 def generate(lengths):
     os.makedirs(GEN, exist_ok=True)
     srcs = []
@@ -95,7 +115,22 @@ def generate(lengths):
                 f"  return &k;\n}}\n}}  // namespace gfc\n")
         _write_if_changed(path, text)
         srcs.append(path)
-    decl = "".join(f"const RowKernels* gfc_row_entry_{n}();\n" for n in lengths)
+    buckets = rg_buckets(lengths)
+    for k, ns in enumerate(buckets):
+        lens = ", ".join(f"RowLen<{choose_factors(n)[0]}, {choose_factors(n)[1]}>" for n in ns)
+        path = os.path.join(GEN, f"row_rgm_{k}.hip")
+        text = (f'#include "gfc_row.h"\n'
+                f"namespace gfc {{\n"
+                f"using RgmK{k} = RowMulti<{lens}>;\n"
+                f"const RgMulti* gfc_rgm_entry_{k}() {{\n"
+                f"  static const RgMulti m{{{k}, &RgmK{k}::fwd, &RgmK{k}::inv}};\n"
+                f"  return &m;\n}}\n}}  // namespace gfc\n")
+        _write_if_changed(path, text)
+        srcs.append(path)
+    rgm_decl = "".join(f"const RgMulti* gfc_rgm_entry_{k}();\n" for k in range(len(buckets)))
+    rgm_cases = "".join(f"    case {n}: return gfc_rgm_entry_{k}();\n"
+                        for k, ns in enumerate(buckets) for n in ns)
+    decl = rgm_decl + "".join(f"const RowKernels* gfc_row_entry_{n}();\n" for n in lengths)
     calls = ",\n      ".join(f"gfc_row_entry_{n}()" for n in lengths)
     table = (f'#include "gfc_internal.h"\nnamespace gfc {{\n{decl}'
              f"static const RowKernels* const* table() {{\n"
@@ -105,7 +140,9 @@ def generate(lengths):
              f"const RowKernels* find_row_kernels(int N) {{\n"
              f"  for (int i = 0; i < {len(lengths)}; ++i)\n"
              f"    if (table()[i]->N == N) return table()[i];\n"
-             f"  return nullptr;\n}}\n}}  // namespace gfc\n")
+             f"  return nullptr;\n}}\n"
+             f"const RgMulti* find_rg_multi(int N) {{\n  switch (N) {{\n{rgm_cases}"
+             f"    default: return nullptr;\n  }}\n}}\n}}  // namespace gfc\n")
     tpath = os.path.join(GEN, "row_table.hip")
     _write_if_changed(tpath, table)
     # z transforms of volumes: one unit for all depths (small kernels)

@@ -63,13 +63,14 @@ struct RowInvArgs {
   // volumes: the image index runs over (volume, z), z < zd; T2 planes [B][zp][H+1][NHP],
   // partials [B][nparts] per volume (zd = zp = 1 for images)
   int zd, zp;
+  int N;              // row length (the ragged launches covering several lengths branch on it)
 };
 
-// Laplacian input: SB[y][0] <- sum_{y' <= y} SB[y'][0] for y in [0, H) of every image, so the
-// column pass's split form (1 - S) b reproduces the DC column of L (float64 running sums).
 // Bins kLowBins < l <= K of T1 and SB in the split form, as direct float32 sums over the
 // (edited) gradient rows; run after the row pass on the same stream. No-op for K <= kLowBins.
 hipError_t launch_low_ext(const RowFwdArgs& a, int B, hipStream_t s);
+// Laplacian input: SB[y][0] <- sum_{y' <= y} SB[y'][0] for y in [0, H) of every image, so the
+// column pass's split form (1 - S) b reproduces the DC column of L (float64 running sums).
 hipError_t launch_sb_prefix(f2* SB, int H, int KP, long long img_sb, int B, hipStream_t s);
 
 // Colour correction of eq. (25) in place on u [B][npix]: every workgroup of image b reduces
@@ -225,6 +226,13 @@ struct RowKernels {
   hipError_t (*rg_inv)(const RgBase&, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
 };
 const RowKernels* find_row_kernels(int N);
+// ragged launches that cover several row lengths of one workgroup size (half support only)
+struct RgMulti {
+  int id;  // distinct per group of lengths
+  hipError_t (*fwd)(const RgBase&, const RgRowFwd*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*inv)(const RgBase&, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
+};
+const RgMulti* find_rg_multi(int N);
 int row_kernel_count();
 const RowKernels* row_kernel_at(int i);
 

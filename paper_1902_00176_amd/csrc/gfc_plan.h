@@ -150,6 +150,7 @@ inline RowInvArgs row_inv_args(const gfc_plan_s* p, const f2* T, float* u,
   v.mom = nullptr;
   v.zd = 1;
   v.zp = 1;
+  v.N = p->N;
   return v;
 }
 

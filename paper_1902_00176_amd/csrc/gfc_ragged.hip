@@ -2,13 +2,18 @@
 //
 // Each image keeps its own plan (its torus, float64 column tables and row twiddles; images
 // with the same sizes share one). The three passes run over all images at once:
-//   row pass      one launch per distinct row length N (the FFT code is specialised on N),
-//                 spread over four streams, each workgroup one (image, strip block) item;
-//                 then one launch of the extra split row bins of thin images (K > 4);
+//   row pass      the FFT code is specialised on the row length N; one launch covers the
+//                 lengths of one group of about 12 (one workgroup size, half support
+//                 2 W <= N), else one launch per length; each workgroup one (image, strip block)
+//                 item; then one launch of the extra split row bins of thin images (K > 4);
 //   column pass   one launch for the tiles holding columns l <= K and one for the rest,
-//                 covering every image, each workgroup one (image, column tile) item;
+//                 each workgroup one (image, column tile) item;
 //   inverse row   as the row pass.
-// Work items are ordered largest image first so the small ones fill the tail of a launch.
+// The launches are dealt to four streams (largest estimated bytes first, each to the least
+// loaded stream), and every stream runs the three passes for its own images: the
+// streams never wait for each other, so one stream's column pass overlaps another's row
+// launches. Work items are ordered largest image first so the small ones fill the tail of
+// a launch.
 // The whole sequence is captured once into a HIP graph and replayed by every later call
 // with the same buffers. Per image the arithmetic is the plain path's, so a ragged solve
 // equals solving each image with its plan (gfc_ragged_solve_sequential).
@@ -59,16 +64,21 @@ struct gfc_ragged_s {
   RgRowInv* tab_i = nullptr;
   RgItem* items = nullptr;
   struct Group {
-    const RowKernels* rk;
+    const RowKernels* rk;  // one row length, or
+    const RgMulti* mk;     // several lengths of one workgroup size (half support)
     int f_off, f_n, i_off, i_n;
     bool half;  // every image of the group has 2 W <= N
   };
-  std::vector<Group> groups;  // one per distinct N
-  int x_off = 0, x_n = 0;  // low-bin extension items (image, row) of images with K > kLowBins
-  int c_low_off = 0, c_low_n = 0, c_rest_off = 0, c_rest_n = 0;
-  int c_threads = 64;
-  size_t c_shm = 0;
-  bool c_tail = false;
+  std::vector<Group> groups;  // one per multi-length launch, or per row length
+  struct Lane {                // the work of one stream
+    std::vector<int> groups;   // its row lengths
+    int x_off = 0, x_n = 0;    // low-bin extension items (image, row) of images with K > 4
+    int c_low_off = 0, c_low_n = 0, c_rest_off = 0, c_rest_n = 0;
+    int c_threads = 64;
+    size_t c_shm = 0;
+    bool c_tail = false;
+  };
+  Lane lanes[4];
 
   // launch machinery
   hipStream_t side[kRgStreams - 1] = {};
@@ -92,8 +102,10 @@ void release(gfc_ragged_s* r) {
   r->plans.clear();
 }
 
-// Enqueue the three passes on `main` (and the side streams, joined back to `main`).
+// Enqueue the three passes of every stream's images on `main` and the side streams, joined
+// back to `main`.
 gfc_status enqueue(gfc_ragged_s* r, const RgBase& base, hipStream_t main) {
+  static_assert(kRgStreams == 4, "one Lane per stream");
   hipStream_t st[kRgStreams] = {main, r->side[0], r->side[1], r->side[2]};
   auto fork = [&](int k) -> bool {  // side streams wait for main
     if (hipEventRecord(r->ev[k], main) != hipSuccess) return false;
@@ -109,27 +121,32 @@ gfc_status enqueue(gfc_ragged_s* r, const RgBase& base, hipStream_t main) {
     return true;
   };
   if (!fork(0)) return GFC_E_HIP;
-  for (size_t g = 0; g < r->groups.size(); ++g) {
-    const auto& G = r->groups[g];
-    if (G.f_n > 0 &&
-        G.rk->rg_fwd(base, r->tab_f, r->items + G.f_off, G.f_n, G.half, st[g % kRgStreams]) != hipSuccess)
+  for (int k = 0; k < kRgStreams; ++k) {
+    const auto& Ln = r->lanes[k];
+    if (Ln.groups.empty()) continue;
+    for (int g : Ln.groups) {
+      const auto& G = r->groups[g];
+      if (G.f_n == 0) continue;
+      const hipError_t e =
+          G.mk ? G.mk->fwd(base, r->tab_f, r->items + G.f_off, G.f_n, st[k])
+               : G.rk->rg_fwd(base, r->tab_f, r->items + G.f_off, G.f_n, G.half, st[k]);
+      if (e != hipSuccess) return GFC_E_HIP;
+    }
+    if (launch_low_ext_rg(base, r->tab_f, r->items + Ln.x_off, Ln.x_n, st[k]) != hipSuccess)
       return GFC_E_HIP;
+    if (launch_col_fwd_rg(base, r->tab_c, r->items + Ln.c_low_off, Ln.c_low_n,
+                          r->items + Ln.c_rest_off, Ln.c_rest_n, kRgColRows, Ln.c_tail,
+                          Ln.c_threads, Ln.c_shm, st[k]) != hipSuccess)
+      return GFC_E_HIP;
+    for (int g : Ln.groups) {
+      const auto& G = r->groups[g];
+      if (G.i_n == 0) continue;
+      const hipError_t e = G.mk ? G.mk->inv(base, r->tab_i, r->items + G.i_off, G.i_n, st[k])
+                                : G.rk->rg_inv(base, r->tab_i, r->items + G.i_off, G.i_n, st[k]);
+      if (e != hipSuccess) return GFC_E_HIP;
+    }
   }
   if (!join(kRgStreams)) return GFC_E_HIP;
-  if (launch_low_ext_rg(base, r->tab_f, r->items + r->x_off, r->x_n, main) != hipSuccess)
-    return GFC_E_HIP;
-  if (launch_col_fwd_rg(base, r->tab_c, r->items + r->c_low_off, r->c_low_n,
-                        r->items + r->c_rest_off, r->c_rest_n, kRgColRows, r->c_tail,
-                        r->c_threads, r->c_shm, main) != hipSuccess)
-    return GFC_E_HIP;
-  if (!fork(2 * kRgStreams)) return GFC_E_HIP;
-  for (size_t g = 0; g < r->groups.size(); ++g) {
-    const auto& G = r->groups[g];
-    if (G.i_n > 0 &&
-        G.rk->rg_inv(base, r->tab_i, r->items + G.i_off, G.i_n, st[g % kRgStreams]) != hipSuccess)
-      return GFC_E_HIP;
-  }
-  if (!join(3 * kRgStreams)) return GFC_E_HIP;
   return GFC_OK;
 }
 
@@ -243,29 +260,60 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
   });
   std::vector<RgItem> items;
   r->groups.clear();
-  std::vector<int> lengths;
+  // launch key of an image: its multi-length group (half support) or its row length
+  auto key_of = [&](int i) -> long long {
+    const RgMulti* m = 2 * r->W[i] <= r->N[i] ? find_rg_multi(r->N[i]) : nullptr;
+    return m ? -1 - (long long)m->id : (long long)r->N[i];
+  };
+  auto bytes_of = [&](int i) {
+    return 12.0 * r->H[i] * r->W[i] + 32.0 * (r->H[i] + 1) * (r->N[i] / 2 + 1);
+  };
+  double total = 0.0;
+  for (int i = 0; i < B; ++i) total += bytes_of(i);
+  // launches: the images of one key, largest first, cut into chunks of at most an eighth of
+  // the batch's bytes so that the streams can be balanced
+  const double cap = total / (2 * kRgStreams);
+  std::vector<long long> keys;
   for (int i : order)
-    if (std::find(lengths.begin(), lengths.end(), r->N[i]) == lengths.end())
-      lengths.push_back(r->N[i]);
-  for (int n : lengths) {
+    if (std::find(keys.begin(), keys.end(), key_of(i)) == keys.end()) keys.push_back(key_of(i));
+  std::vector<std::vector<int>> chunks;
+  std::vector<double> gbytes;
+  for (long long key : keys) {
+    std::vector<int> cur;
+    double cb = 0.0;
+    for (int i : order) {
+      if (key_of(i) != key) continue;
+      if (!cur.empty() && cb + bytes_of(i) > cap) {
+        chunks.push_back(cur);
+        gbytes.push_back(cb);
+        cur.clear();
+        cb = 0.0;
+      }
+      cur.push_back(i);
+      cb += bytes_of(i);
+    }
+    chunks.push_back(cur);
+    gbytes.push_back(cb);
+  }
+  for (const auto& ch : chunks) {
     gfc_ragged_s::Group g{};
-    const int first = *std::find_if(order.begin(), order.end(), [&](int i) { return r->N[i] == n; });
+    const int first = ch.front();
     g.rk = r->plans[r->plan_of[first]]->rk;
-    const int slots = g.rk->slots;
+    g.mk = key_of(first) < 0 ? find_rg_multi(r->N[first]) : nullptr;
     g.f_off = int(items.size());
     g.half = true;
-    for (int i : order) {
-      if (r->N[i] != n) continue;
-      g.half = g.half && 2 * r->W[i] <= n;
+    for (int i : ch) {
+      g.half = g.half && 2 * r->W[i] <= r->N[i];
       const gfc_plan_s* p = r->plans[r->plan_of[i]];
+      const int slots = p->rk->slots;
       const int nb = (p->nfslots + slots - 1) / slots;
       for (int k = 0; k < nb; ++k) items.push_back(RgItem{i, k});
     }
     g.f_n = int(items.size()) - g.f_off;
     g.i_off = int(items.size());
-    for (int i : order) {
-      if (r->N[i] != n) continue;
+    for (int i : ch) {
       const gfc_plan_s* p = r->plans[r->plan_of[i]];
+      const int slots = p->rk->slots;
       const int need = (p->npairs + p->row_ppw - 1) / p->row_ppw;
       const int nb = (need + slots - 1) / slots;
       for (int k = 0; k < nb; ++k) items.push_back(RgItem{i, k});
@@ -273,39 +321,58 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
     g.i_n = int(items.size()) - g.i_off;
     r->groups.push_back(g);
   }
-  r->x_off = int(items.size());
-  for (int i : order) {
-    const gfc_plan_s* p = r->plans[r->plan_of[i]];
-    if (p->K > kLowBins)
-      for (int y = 0; y <= p->H; ++y) items.push_back(RgItem{i, y});
+  // launches to streams: largest first, each to the least loaded stream
+  std::vector<int> gorder(chunks.size());
+  for (size_t g = 0; g < gorder.size(); ++g) gorder[g] = int(g);
+  std::stable_sort(gorder.begin(), gorder.end(), [&](int a, int b) { return gbytes[a] > gbytes[b]; });
+  double load[kRgStreams] = {};
+  std::vector<int> lane_img(B, 0);
+  for (auto& Ln : r->lanes) Ln = gfc_ragged_s::Lane{};
+  for (int g : gorder) {
+    const int k = int(std::min_element(load, load + kRgStreams) - load);
+    load[k] += gbytes[g];
+    r->lanes[k].groups.push_back(g);
+    for (int i : chunks[g]) lane_img[i] = k;
   }
-  r->x_n = int(items.size()) - r->x_off;
-  int threads = 64;
-  size_t shm = 0;
-  bool tail = false;
-  r->c_low_off = int(items.size());
-  for (int i : order) {
-    const gfc_plan_s* p = r->plans[r->plan_of[i]];
-    const int nlow = std::min(p->ntiles_f, (p->K + 1 + p->gf.C - 1) / p->gf.C);
-    for (int k = 0; k < nlow; ++k) items.push_back(RgItem{i, k});
+  auto lane_of = [&](int i) { return lane_img[i]; };
+  // per stream: extension items, column items (low tiles, then the rest), workgroup shape
+  for (int k = 0; k < kRgStreams; ++k) {
+    auto& Ln = r->lanes[k];
+    Ln.x_off = int(items.size());
+    for (int i : order) {
+      const gfc_plan_s* p = r->plans[r->plan_of[i]];
+      if (lane_of(i) == k && p->K > kLowBins)
+        for (int y = 0; y <= p->H; ++y) items.push_back(RgItem{i, y});
+    }
+    Ln.x_n = int(items.size()) - Ln.x_off;
+    Ln.c_low_off = int(items.size());
+    for (int i : order) {
+      if (lane_of(i) != k) continue;
+      const gfc_plan_s* p = r->plans[r->plan_of[i]];
+      const int nlow = std::min(p->ntiles_f, (p->K + 1 + p->gf.C - 1) / p->gf.C);
+      for (int t = 0; t < nlow; ++t) items.push_back(RgItem{i, t});
+    }
+    Ln.c_low_n = int(items.size()) - Ln.c_low_off;
+    Ln.c_rest_off = int(items.size());
+    for (int i : order) {
+      if (lane_of(i) != k) continue;
+      const gfc_plan_s* p = r->plans[r->plan_of[i]];
+      const int nlow = std::min(p->ntiles_f, (p->K + 1 + p->gf.C - 1) / p->gf.C);
+      for (int t = nlow; t < p->ntiles_f; ++t) items.push_back(RgItem{i, t});
+    }
+    Ln.c_rest_n = int(items.size()) - Ln.c_rest_off;
+    Ln.c_threads = 64;
+    Ln.c_shm = 0;
+    Ln.c_tail = false;
+    for (int i = 0; i < B; ++i) {
+      if (lane_of(i) != k) continue;
+      const gfc_plan_s* p = r->plans[r->plan_of[i]];
+      if (p->gf.Lseg != kRgColRows) return GFC_E_SIZE;
+      Ln.c_threads = std::max(Ln.c_threads, (p->gf.C * p->gf.nseg + 63) / 64 * 64);
+      Ln.c_shm = std::max(Ln.c_shm, size_t(2 * p->gf.nseg * p->gf.C) * 2 * sizeof(double));
+      Ln.c_tail = Ln.c_tail || p->gf.tail;
+    }
   }
-  r->c_low_n = int(items.size()) - r->c_low_off;
-  r->c_rest_off = int(items.size());
-  for (int i : order) {
-    const gfc_plan_s* p = r->plans[r->plan_of[i]];
-    const int nlow = std::min(p->ntiles_f, (p->K + 1 + p->gf.C - 1) / p->gf.C);
-    for (int k = nlow; k < p->ntiles_f; ++k) items.push_back(RgItem{i, k});
-  }
-  r->c_rest_n = int(items.size()) - r->c_rest_off;
-  for (const gfc_plan_s* p : r->plans) {
-    if (p->gf.Lseg != kRgColRows) return GFC_E_SIZE;
-    threads = std::max(threads, (p->gf.C * p->gf.nseg + 63) / 64 * 64);
-    shm = std::max(shm, size_t(2 * p->gf.nseg * p->gf.C) * 2 * sizeof(double));
-    tail = tail || p->gf.tail;
-  }
-  r->c_threads = threads;
-  r->c_shm = shm;
-  r->c_tail = tail;
 
   // one device allocation for the tables and the item list
   size_t o = 0;

@@ -413,19 +413,29 @@ __device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
   }
 }
 
+// LDS floats of one slot's plane in the forward row pass: the FFT exchange, or the low-bin
+// lane sums (4 (2K + 1) values over G + 1 lanes) when larger
+template <int N1, int N2>
+constexpr int kFwdPlane =
+    cmax(RowCfg<N1, N2>::LDSC, (4 * (2 * kLowBins + 1) * (RowCfg<N1, N2>::G + 1) + 1) / 2);
+template <int N1, int N2, int SLOTS>
+constexpr int kFwdLds = SLOTS * 2 * kFwdPlane<N1, N2>;  // floats per workgroup
+template <int N1, int N2, int SLOTS>
+constexpr int kInvLds = SLOTS * 2 * RowCfg<N1, N2>::LDSC;
+
+// lds: kFwdLds<N1, N2, SLOTS> floats of the workgroup's LDS
 template <int N1, int N2, int SLOTS, int NB, int EDIT = kEditNone>
-__device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b) {
+__device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, float* lds) {
   using C = RowCfg<N1, N2>;
   constexpr int KL = kLowBins;
   constexpr int NC = 2 * KL + 1;         // low-bin complex values per row
   constexpr int NV = 4 * NC;             // floats per lane to sum: two rows, re and im
   constexpr int RS = C::G + 1;           // LDS stride of one value over the lanes
-  constexpr int PLANE = cmax(C::LDSC, (NV * RS + 1) / 2);
-  __shared__ float s_lds[SLOTS][2 * PLANE];
+  constexpr int PLANE = kFwdPlane<N1, N2>;
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
-  float* re = s_lds[slot];
-  float* im = s_lds[slot] + PLANE;
+  float* re = lds + slot * 2 * PLANE;
+  float* im = re + PLANE;
   const float* gxi = p.gx + b * p.img_in;
   const float* gyi = p.gy + b * p.img_in;
   // volumes: b runs over (volume, z <= zd); the T1 plane is z of zp
@@ -639,9 +649,10 @@ template <int N1, int N2, int SLOTS, int NB, int EDIT>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 __attribute__((amdgpu_waves_per_eu(kFwdWaves<N1, SLOTS, NB, EDIT>)))
 k_row_fwd(RowFwdArgs p) {
+  __shared__ float lds[kFwdLds<N1, N2, SLOTS>];
   int bx, by;
   xcd_contiguous(bx, by);
-  row_fwd_body<N1, N2, SLOTS, NB, EDIT>(p, bx, by);
+  row_fwd_body<N1, N2, SLOTS, NB, EDIT>(p, bx, by, lds);
 }
 
 // ragged batches: one work item (image, block) per workgroup; pointers rebased per image
@@ -655,7 +666,8 @@ k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
   p.gy = base.gy + e.in;
   p.T1 = reinterpret_cast<f2*>(base.ws + e.t);
   p.SB = reinterpret_cast<f2*>(base.ws + e.side);
-  row_fwd_body<N1, N2, SLOTS, NB>(p, it.blk, 0);
+  __shared__ float lds[kFwdLds<N1, N2, SLOTS>];
+  row_fwd_body<N1, N2, SLOTS, NB>(p, it.blk, 0, lds);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -663,17 +675,16 @@ k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
 // Each slot handles p.ppw pairs of rows, two rows per complex inverse FFT.
 // MOM: also the float64 sums of the stored values and their squares, one pair per
 // workgroup (fixed summation order), for the colour correction of eq. (25).
+// lds: kInvLds<N1, N2, SLOTS> floats of the workgroup's LDS
 template <int N1, int N2, int SLOTS, bool MOM = false>
-__device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) {
+__device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, float* lds) {
   using C = RowCfg<N1, N2>;
-  __shared__ float s_re[SLOTS][C::LDSC];
-  __shared__ float s_im[SLOTS][C::LDSC];
   __shared__ double s_mom[SLOTS][2];
   double m1 = 0.0, m2 = 0.0;
   const int slot = threadIdx.x / C::G;
   const int lane = threadIdx.x % C::G;
-  float* re = s_re[slot];
-  float* im = s_im[slot];
+  float* re = lds + slot * C::LDSC;
+  float* im = lds + (SLOTS + slot) * C::LDSC;
   // image b, or slice z = b % zd of volume b / zd (its spectra are plane z of zp)
   const int vol = b / p.zd;
   const rsrc_t rT2 = make_buf(p.T2 + ((long long)vol * p.zp + b % p.zd) * p.img_t2, p.img_t2 * 8);
@@ -755,7 +766,8 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b) 
 template <int N1, int N2, int SLOTS, bool MOM>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_inv(RowInvArgs p) {
-  row_inv_body<N1, N2, SLOTS, MOM>(p, blockIdx.x, blockIdx.y);
+  __shared__ float lds[kInvLds<N1, N2, SLOTS>];
+  row_inv_body<N1, N2, SLOTS, MOM>(p, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int N1, int N2, int SLOTS>
@@ -767,7 +779,8 @@ k_row_inv_rg(RgBase base, const RgRowInv* tab, const RgItem* items) {
   p.T2 = reinterpret_cast<const f2*>(base.ws + e.t);
   p.u = base.u + e.out;
   p.partial = reinterpret_cast<const double*>(base.ws + e.red);
-  row_inv_body<N1, N2, SLOTS>(p, it.blk, 0);
+  __shared__ float lds[kInvLds<N1, N2, SLOTS>];
+  row_inv_body<N1, N2, SLOTS>(p, it.blk, 0, lds);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -998,6 +1011,81 @@ struct RowLaunch {
                            int nitems, hipStream_t s) {
     hipLaunchKernelGGL((k_row_inv_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
                        base, tab, items);
+    return hipGetLastError();
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Ragged batches with many row lengths: one launch runs the items of several lengths, each
+// workgroup branching (uniformly) on its image's N to that length's body. A launch costs a
+// few microseconds of latency however small it is, so a batch of 49 lengths issued per
+// length spends most of its time in launch tails; grouping lengths of one workgroup size
+// cuts the launches per row pass to a handful. The LDS is the largest of the lengths'; the
+// registers are the most any of them needs. Only the half-support forward variant (2 W <= N,
+// every default torus) is grouped.
+template <int N1_, int N2_>
+struct RowLen {
+  static constexpr int N1 = N1_, N2 = N2_, N = N1_ * N2_;
+  static constexpr int SLOTS = RowLaunch<N1_, N2_>::SLOTS;
+  static constexpr int NBH = RowLaunch<N1_, N2_>::NB_HALF;
+  static constexpr int THREADS = SLOTS * RowCfg<N1_, N2_>::G;
+  static constexpr int FWD_LDS = kFwdLds<N1_, N2_, SLOTS>;
+  static constexpr int INV_LDS = kInvLds<N1_, N2_, SLOTS>;
+};
+constexpr int cmax_n(int a) { return a; }
+template <class... T>
+constexpr int cmax_n(int a, int b, T... r) { return cmax_n(cmax(a, b), r...); }
+
+template <class L0, class... Ls>
+__global__ void __launch_bounds__(L0::THREADS)
+k_row_fwd_rgm(RgBase base, const RgRowFwd* tab, const RgItem* items) {
+  static_assert(((Ls::THREADS == L0::THREADS) && ...), "one workgroup size per launch");
+  constexpr int NL = cmax_n(L0::FWD_LDS, Ls::FWD_LDS...);
+  __shared__ float lds[NL];
+  const RgItem it = items[blockIdx.x];
+  const RgRowFwd& e = tab[it.img];
+  RowFwdArgs p = e.a;
+  p.gx = base.gx + e.in;
+  p.gy = base.gy + e.in;
+  p.T1 = reinterpret_cast<f2*>(base.ws + e.t);
+  p.SB = reinterpret_cast<f2*>(base.ws + e.side);
+  const int n = p.N;
+  (void)((n == L0::N && (row_fwd_body<L0::N1, L0::N2, L0::SLOTS, L0::NBH>(p, it.blk, 0, lds),
+                         true)) ||
+         ... ||
+         (n == Ls::N && (row_fwd_body<Ls::N1, Ls::N2, Ls::SLOTS, Ls::NBH>(p, it.blk, 0, lds),
+                         true)));
+}
+
+template <class L0, class... Ls>
+__global__ void __launch_bounds__(L0::THREADS)
+k_row_inv_rgm(RgBase base, const RgRowInv* tab, const RgItem* items) {
+  constexpr int NL = cmax_n(L0::INV_LDS, Ls::INV_LDS...);
+  __shared__ float lds[NL];
+  const RgItem it = items[blockIdx.x];
+  const RgRowInv& e = tab[it.img];
+  RowInvArgs p = e.a;
+  p.T2 = reinterpret_cast<const f2*>(base.ws + e.t);
+  p.u = base.u + e.out;
+  p.partial = reinterpret_cast<const double*>(base.ws + e.red);
+  const int n = p.N;
+  (void)((n == L0::N && (row_inv_body<L0::N1, L0::N2, L0::SLOTS>(p, it.blk, 0, lds), true)) ||
+         ... ||
+         (n == Ls::N && (row_inv_body<Ls::N1, Ls::N2, Ls::SLOTS>(p, it.blk, 0, lds), true)));
+}
+
+template <class L0, class... Ls>
+struct RowMulti {
+  static hipError_t fwd(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+                        int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_fwd_rgm<L0, Ls...>), dim3(nitems), dim3(L0::THREADS), 0, s, base,
+                       tab, items);
+    return hipGetLastError();
+  }
+  static hipError_t inv(const RgBase& base, const RgRowInv* tab, const RgItem* items,
+                        int nitems, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_inv_rgm<L0, Ls...>), dim3(nitems), dim3(L0::THREADS), 0, s, base,
+                       tab, items);
     return hipGetLastError();
   }
 };
