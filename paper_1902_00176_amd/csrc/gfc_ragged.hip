@@ -35,7 +35,7 @@ using namespace gfc;
 namespace {
 constexpr int kRgStreams = 4;       // streams the per-length row launches are spread over
 constexpr int kRgColThreads = 512;  // target workgroup size of the ragged column pass
-constexpr int kRgColRows = 16;      // rows per column-pass thread for every image
+constexpr int kRgColRows = 32;      // rows per column-pass thread for every image
 
 int pow2_floor(int v) {
   int p = 1;
