@@ -630,7 +630,7 @@ struct gfc_plan3_s {
 
 namespace {
 struct Ws3 {
-  size_t t, side, red, total;
+  size_t t, side, red, tot, total;  // tot: one corner-constant sum per volume
 };
 Ws3 ws3_layout(const gfc_plan3_s* q, int B) {
   const gfc_plan_s* p = q->p2;
@@ -639,7 +639,8 @@ Ws3 ws3_layout(const gfc_plan3_s* q, int B) {
   w.t = 0;
   w.side = align256(vols * size_t(p->H + 1) * p->NHP * sizeof(f2));
   w.red = w.side + align256(vols * size_t(p->H) * p->KP * sizeof(f2));
-  w.total = w.red + align256(vols * size_t(p->ntiles_f) * sizeof(double));
+  w.tot = w.red + align256(vols * size_t(p->ntiles_f) * sizeof(double));
+  w.total = w.tot + align256(size_t(B) * sizeof(double));
   return w;
 }
 }  // namespace
@@ -789,11 +790,14 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   z.dout = D;
   st = hip_status(q->zk->run(z, +1, B, s));
   if (st != GFC_OK) return st;
-  // 6. inverse rows of every slice z < D, crop and the corner constant
-  RowInvArgs v = row_inv_args(p, T, u, partial);
+  // 6. the corner constant of each volume, then the inverse rows of every slice z < D, crop
+  double* total = reinterpret_cast<double*>(ws + w.tot);
+  st = hip_status(launch_partial_sums(partial, P * p->ntiles_f, total, B, s));
+  if (st != GFC_OK) return st;
+  RowInvArgs v = row_inv_args(p, T, u, total);
   v.zd = D;
   v.zp = P;
-  v.nparts = P * p->ntiles_f;
+  v.nparts = 1;
   return hip_status(p->rk->inv(v, B * D, s));
 }
 

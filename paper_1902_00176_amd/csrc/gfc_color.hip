@@ -156,4 +156,29 @@ hipError_t launch_sb_volume(const f2* T, f2* SB, int H, int KP, int P, int NHP,
   return hipGetLastError();
 }
 
+// Volumes: the corner constant is the sum of one partial per (plane, column tile), P times
+// more than for an image. Every inverse row workgroup of a volume would re-read them all, so
+// they are summed once here (fixed order: thread-strided sums, then an LDS tree).
+__global__ void __launch_bounds__(kScanThreads)
+k_partial_sums(const double* partial, int nparts, double* total) {
+  __shared__ double sh[kScanThreads];
+  const int t = threadIdx.x;
+  const double* in = partial + (long long)blockIdx.x * nparts;
+  double a = 0.0;
+  for (int j = t; j < nparts; j += kScanThreads) a += in[j];
+  sh[t] = a;
+  __syncthreads();
+  for (int d = kScanThreads / 2; d > 0; d >>= 1) {
+    if (t < d) sh[t] += sh[t + d];
+    __syncthreads();
+  }
+  if (t == 0) total[blockIdx.x] = sh[0];
+}
+
+hipError_t launch_partial_sums(const double* partial, int nparts, double* total, int B,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_partial_sums, dim3(B), dim3(kScanThreads), 0, s, partial, nparts, total);
+  return hipGetLastError();
+}
+
 }  // namespace gfc

@@ -211,6 +211,9 @@ struct ZKernels {
 };
 const ZKernels* find_z_kernels(int P);
 // volumes: SB[vol * P + kz][y][0] = (kz == 0) ? sum_{y' <= y} T[vol][0][y'][0] : 0, y < H
+// total[b] = sum of partial[b][0 .. nparts) in a fixed order, one workgroup per volume
+hipError_t launch_partial_sums(const double* partial, int nparts, double* total, int B,
+                               hipStream_t s);
 hipError_t launch_sb_volume(const f2* T, f2* SB, int H, int KP, int P, int NHP,
                             long long vol_stride, long long img_sb, int B, hipStream_t s);
 

@@ -27,7 +27,9 @@ __global__ void __launch_bounds__((ZCfg<P1, P2>::TL * ZCfg<P1, P2>::G))
 k_zfft(ZfftArgs a) {
   using C = ZCfg<P1, P2>;
   constexpr int P = C::P, G = C::G, TL = C::TL, NT = TL * G;
-  __shared__ float s_lds[TL][2 * C::S];
+  // one column per row of s_lds; the odd row length puts the TL columns of one plane in
+  // different banks for the coalesced load and store phases
+  __shared__ float s_lds[TL][2 * C::S + 1];
   const int t = threadIdx.x;
   const int y = blockIdx.y, vol = blockIdx.z;
   const int l0 = blockIdx.x * TL;
