@@ -42,8 +42,10 @@ def smooth_number_at_least(n: int, even: bool = True) -> int:
 
 
 def default_grid(H: int, W: int) -> tuple[int, int]:
-    """Default torus size: smallest even 2/3/5-smooth M >= 2H and N >= 2W."""
-    return smooth_number_at_least(2 * H), smooth_number_at_least(2 * W)
+    """Default torus size: smallest even 2/3/5-smooth M >= max(2H, H + 2) and
+    N >= max(2W, W + 2, 16) (16: the shortest row FFT of the library)."""
+    return (smooth_number_at_least(max(2 * H, H + 2)),
+            smooth_number_at_least(max(2 * W, W + 2, 16)))
 
 
 def image_rngs(seed: int, count: int) -> list[np.random.Generator]:

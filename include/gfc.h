@@ -59,7 +59,8 @@ typedef enum {
 
 /*
  * Create a plan for H x W images solved on an M x N torus (Sec. 2.3.2 zero padding).
- * M = N = 0 selects the default torus: the smallest even 2/3/5-smooth M >= 2H, N >= 2W.
+ * M = N = 0 selects the default torus: the smallest even 2/3/5-smooth M >= max(2H, H + 2),
+ * N >= max(2W, W + 2, 16) (16 is the shortest row FFT).
  * Requires M >= H + 2, N >= W + 2 and N a supported row-FFT length (even, 2/3/5-smooth,
  * listed by gfc_supported_length). Host-only: touches no GPU. *out receives the plan.
  */

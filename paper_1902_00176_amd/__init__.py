@@ -134,7 +134,7 @@ def default_grid(H: int, W: int) -> tuple[int, int]:
             if r == 1 and m % 2 == 0:
                 return m
             m += 1
-    return sm(2 * H), sm(2 * W)
+    return sm(max(2 * H, H + 2)), sm(max(2 * W, W + 2, 16))
 
 
 def _stream_ptr(torch, device, stream):

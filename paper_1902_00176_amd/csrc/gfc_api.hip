@@ -178,8 +178,10 @@ gfc_status gfc_plan_create(gfc_plan_t* out, int H, int W, int M, int N, unsigned
   if (H < 1 || W < 1 || M < 0 || N < 0 || flags != GFC_FLAG_NONE) return GFC_E_ARG;
   // the column pass holds a whole column in one workgroup: at most 1024 segments of 32 rows
   if (H >= (1 << 15) || W > (1 << 15)) return GFC_E_SIZE;
-  if (M == 0) M = smooth_at_least(2L * H);
-  if (N == 0) N = smooth_at_least(2L * W);
+  // default torus: the smallest even 2/3/5-smooth M >= 2H and N >= 2W, at least H + 2 and
+  // W + 2, and N at least the shortest row FFT (16)
+  if (M == 0) M = smooth_at_least(std::max(2L * H, H + 2L));
+  if (N == 0) N = smooth_at_least(std::max({2L * W, W + 2L, 16L}));
   if (M < H + 2 || N < W + 2) return GFC_E_SIZE;
   const RowKernels* rk = find_row_kernels(N);
   if (!rk) return GFC_E_SIZE;

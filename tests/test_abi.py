@@ -32,6 +32,10 @@ def test_status_strings():
     (0, 5, 0, 0, 1), (5, -1, 0, 0, 1), (10, 10, 11, 24, 2), (10, 10, 24, 11, 2),
     (10, 10, 24, 22, 2),   # 22 = 2 * 11 is not 2/3/5-smooth: no row FFT
     (10, 10, 12, 24, 0), (801, 1200, 0, 0, 0), (64, 64, 128, 128, 0),
+    (1, 1, 0, 0, 0), (4, 4, 0, 0, 0), (32767, 4, 0, 0, 0),  # tiny and tallest default tori
+    (1 << 15, 4, 0, 0, 2), (4, (1 << 15) + 1, 0, 0, 2),    # past the height / width limits
+    (10, 1300, 0, 0, 2),   # default N = 2600 has no row FFT
+    (10, 2399, 0, 2400, 2),  # N < W + 2
 ])
 def test_plan_create_validation(H, W, M, N, status):
     L = gfc.lib()

@@ -117,6 +117,25 @@ def test_forward_more_split_bins(K):
     assert max(per_image_rel(u, u4)) <= TOL
 
 
+@pytest.mark.parametrize("H,W", [(1, 1), (4, 4), (32767, 4)])
+def test_default_tori_at_the_size_limits(H, W):
+    """Default tori of the smallest images and of the tallest one a plan accepts (1024
+    column segments of 32 rows in one workgroup), forward and backward."""
+    p = gfc.Plan(H, W, tuned=False)
+    M, N = p.M, p.N
+    _say(f"default torus H={H} W={W} -> M={M} N={N}")
+    gx, gy = _rand_fields(H + 5 * W, 2, H, W)
+    u = _gpu_solve(gx, gy, M, N)
+    errs = per_image_rel(u, O.solve_fft(gx, gy, M, N))
+    assert max(errs) <= TOL, errs
+    du = (0.1 * np.random.default_rng(H).normal(size=(2, H, W)) + 0.02).astype(np.float32)
+    dgx, dgy = _gpu_backward(du, M, N)
+    rx, ry = O.solve_backward(du, M, N)
+    for i in range(2):
+        e = rel_l2(np.concatenate([dgx[i], dgy[i]]), np.concatenate([rx[i], ry[i]]))
+        assert e <= TOL, (i, e)
+
+
 def test_forward_small64_workload():
     w = synth.make_workload("small64")
     _say("forward parity small64")
