@@ -306,3 +306,42 @@ def test_adjoint_identity_on_gpu():
     lhs = np.sum(u * du)
     rhs = np.sum(gx.astype(np.float64) * dgx) + np.sum(gy.astype(np.float64) * dgy)
     assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs))
+
+
+def test_solves_capture_into_a_graph_and_replay():
+    """Forward and backward solves enqueue kernels and events only, so they can be captured
+    into a HIP graph (the forward column pass forks its low tiles to the plan's side stream
+    and joins back). Each replay, with eager work and new inputs between replays, equals the
+    eager solve of the same inputs bit for bit."""
+    H, W, M, N, B = 129, 200, 260, 400, 3
+    _say("graph capture of forward and backward solves")
+    plan = gfc.Plan(H, W, M, N, tuned=False).build()
+    gx, gy = _rand_fields(91, B, H, W)
+    tx = torch.from_numpy(gx).cuda()
+    ty = torch.from_numpy(gy).cuda()
+    u = torch.empty_like(tx)
+    ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device="cuda")
+    ws_e = torch.empty_like(ws)
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        plan.solve(tx, ty, out=u, workspace=ws)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.solve(tx, ty, out=u, workspace=ws)
+        dgx, dgy = plan.backward(u, workspace=ws)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        scale = float(rng.uniform(0.5, 2.0))
+        tx.copy_(torch.from_numpy(gx * scale))
+        ty.copy_(torch.from_numpy(gy[::-1].copy()))
+        g.replay()
+        torch.cuda.synchronize()
+        ue = plan.solve(tx, ty, workspace=ws_e)
+        ex, ey = plan.backward(ue, workspace=ws_e)
+        torch.cuda.synchronize()
+        assert torch.equal(u, ue), rep
+        assert torch.equal(dgx, ex) and torch.equal(dgy, ey), rep
