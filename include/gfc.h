@@ -28,7 +28,9 @@
  *    call complete in order (graph capture follows the fork). Asynchronous kernel errors
  *    surface as GFC_E_HIP on a later call.
  *  - A plan owns its device tables (created by gfc_green_build) and is immutable after
- *    that call, so it may be used from several streams with separate workspaces.
+ *    that call, so it may be used from several streams with separate workspaces, also
+ *    from several host threads (the side-stream fork and join of a call are enqueued
+ *    under a per-plan lock; the side stream serialises the low tiles of concurrent calls).
  *  - Errors are returned as status codes; nothing is ever thrown across this ABI.
  */
 #ifndef GFC_H_

@@ -397,6 +397,7 @@ gfc_status gfc_solve_batch_stage(gfc_plan_t p, int stage, const float* gx, const
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 2) {
+    std::lock_guard<std::mutex> fork_lock(p->fork_mtx);
     const gfc_status st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s,
                                                     p->side, p->ev_fork, p->ev_join));
     if (st != GFC_OK) return st;
@@ -445,8 +446,11 @@ static gfc_status solve_forward(gfc_plan_t p, const float* gx, const float* gy, 
     st = hip_status(launch_sb_prefix(SB, p->H, p->KP, f.img_sb, B, s));
     if (st != GFC_OK) return st;
   }
-  st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s, p->side, p->ev_fork,
-                                 p->ev_join));
+  {
+    std::lock_guard<std::mutex> fork_lock(p->fork_mtx);
+    st = hip_status(launch_col_fwd(col_fwd_args(p, T, SB, partial), B, s, p->side, p->ev_fork,
+                                   p->ev_join));
+  }
   if (st != GFC_OK) return st;
   RowInvArgs v = row_inv_args(p, T, u, partial);
   const bool color = I_mean != nullptr;
@@ -785,7 +789,10 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   ColFwdArgs c = col_fwd_args(p, T, SB, partial);
   c.cc = q->cc;
   c.zp = P;
-  st = hip_status(launch_col_fwd(c, B * P, s, p->side, p->ev_fork, p->ev_join));
+  {
+    std::lock_guard<std::mutex> fork_lock(p->fork_mtx);
+    st = hip_status(launch_col_fwd(c, B * P, s, p->side, p->ev_fork, p->ev_join));
+  }
   if (st != GFC_OK) return st;
   // 5. inverse z transform: P planes in, the D planes of the volume out
   z.din = P;

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <mutex>
 
 #include "gfc.h"
 #include "gfc_internal.h"
@@ -45,6 +46,9 @@ struct gfc_plan_s {
   // a side stream for the forward column pass's low tiles, joined back with two events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // serialises the fork/join enqueue of calls from several host threads on one plan (the
+  // events are re-recorded by every call)
+  std::mutex fork_mtx;
 };
 
 namespace gfc {

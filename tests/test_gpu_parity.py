@@ -345,3 +345,40 @@ def test_solves_capture_into_a_graph_and_replay():
         torch.cuda.synchronize()
         assert torch.equal(u, ue), rep
         assert torch.equal(dgx, ex) and torch.equal(dgy, ey), rep
+
+
+def test_one_plan_from_several_host_threads():
+    """Two host threads solve with one plan on their own streams and workspaces, many calls
+    each; every result equals the single-threaded solve of the same input bit for bit."""
+    import threading
+    H, W, M, N, B = 129, 200, 260, 400, 2
+    _say("one plan, two host threads")
+    plan = gfc.Plan(H, W, M, N, tuned=False).build()
+    gx, gy = _rand_fields(97, 2 * B, H, W)
+    tx = torch.from_numpy(gx).cuda()
+    ty = torch.from_numpy(gy).cuda()
+    ref = plan.solve(tx, ty)
+    torch.cuda.synchronize()
+    errors = []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device="cuda")
+            out = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+            sl = slice(k * B, (k + 1) * B)
+            with torch.cuda.stream(st):
+                for _ in range(50):
+                    plan.solve(tx[sl], ty[sl], out=out, workspace=ws)
+            st.synchronize()
+            if not torch.equal(out, ref[sl]):
+                errors.append(k)
+        except Exception as e:  # noqa: BLE001
+            errors.append(repr(e))
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors
