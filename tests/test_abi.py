@@ -142,3 +142,15 @@ def test_plan_parameters_round_trip_and_low_bins():
                             ((16, 1200, 32, 2400), 8), ((32, 1200, 64, 2400), 4),
                             ((3, 1250, 8, 2400), 32), ((5000, 6, 10000, 16), 4)):
         assert gfc.Plan(H, W, M, N, tuned=False).get_param("low_bins") == K, (H, W, M, N)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """The product path has no fallback: without the HIP library every entry raises."""
+    monkeypatch.setattr(gfc, "_lib", None)
+    monkeypatch.setattr(gfc, "_LIB_PATH", str(tmp_path / "libgfc.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        gfc.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        gfc.Plan(64, 64)
+    with pytest.raises(RuntimeError, match="missing"):
+        gfc.Ragged([(64, 64, 0, 0)])
