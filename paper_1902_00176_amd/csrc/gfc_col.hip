@@ -541,14 +541,19 @@ void launch_fwd_tiles(const ColFwdArgs& a, int ntiles, int nlow, int B, size_t s
 // Tiles that hold columns l <= K are launched separately so the split-input path costs
 // no registers in the others. Given a side stream and two events, the few low tiles run
 // there, beside the other tiles, and `s` waits for them: they are a small, latency-bound
-// launch that would otherwise run alone.
+// launch that would otherwise run alone. The fork and join cost about 30 us of latency, so
+// batches whose spectra are small (under kSideMinBytes) launch everything on `s`: that
+// halved the column pass of a 64x64 solve and took 5 % off a 48-image 256x256 batch, while
+// 512x512 x 96 and 801x1200 x 100 keep the side stream (2-3 % faster with it).
+constexpr long long kSideMinBytes = 100LL << 20;
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t side,
                           hipEvent_t fork, hipEvent_t join) {
   const size_t shm = size_t(2 * a.nseg * a.C) * sizeof(dc);
   const int ntiles = (a.NH + a.C - 1) / a.C;
   const int nlow = std::min(ntiles, (a.K + 1 + a.C - 1) / a.C);
   const bool tail = a.Rp != a.nseg * a.Lseg;
-  const bool split = side && fork && join && nlow > 0 && ntiles > nlow;
+  const bool split = side && fork && join && nlow > 0 && ntiles > nlow &&
+                     (long long)B * a.img_t * 8 >= kSideMinBytes;
   hipStream_t s_low = s;
   if (split) {
     hipError_t e = hipEventRecord(fork, s);
