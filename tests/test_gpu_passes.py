@@ -1,0 +1,147 @@
+"""Pass-level GPU checks: the forward row pass and the inverse row pass, each alone, through
+gfc_solve_batch_stage, against float64 numpy transforms of the same inputs. The intermediate
+layout is the library's workspace (spectra T [B][H+1][NHP] complex64 from offset 0; the
+split side array SB [B][H][KP] at the next 256-byte boundary; column partials after it), so
+these tests know that layout on purpose."""
+import ctypes
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gfc_synth as synth
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1902_00176_amd as gfc  # noqa: E402
+
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(gfc.lib_path()):
+        pytest.fail("libgfc.so is not built: the HIP path must exist where a GPU is present")
+
+
+def _align256(n):
+    return (n + 255) // 256 * 256
+
+
+def _fields(seed, B, H, W):
+    rng = np.random.default_rng(seed)
+    gx = np.empty((B, H, W), np.float32)
+    gy = np.empty((B, H, W), np.float32)
+    for i in range(B):
+        a, b = synth.forward_gradient(synth.gaussian_sum_field(rng, H, W))
+        gx[i] = a + 0.01 * rng.normal(size=(H, W))
+        gy[i] = b
+    return gx, gy
+
+
+def _stage(plan, k, gx, gy, u, B, ws):
+    st = torch.cuda.current_stream()
+    r = gfc.lib().gfc_solve_batch_stage(plan.handle, k, gx.data_ptr(), gy.data_ptr(),
+                                        u.data_ptr(), B, ws.data_ptr(), ws.numel(),
+                                        ctypes.c_void_p(st.cuda_stream))
+    assert r == 0, gfc.lib().gfc_status_str(r)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("H,W,M,N,K", [(33, 70, 35, 72, 4), (129, 200, 260, 400, 4),
+                                       (801, 1200, 1620, 2400, 4), (40, 300, 84, 640, 16),
+                                       (3, 1250, 8, 2400, 32)])
+def test_forward_row_pass_alone(H, W, M, N, K):
+    """Row pass (divergence fused into the row R2C, eq. (3) and the row half of F(L) in
+    eq. (23)): T1[y, l] = L^[y, l] for l > K, and the split form (1 - w^l) Ex^[y, l] with
+    SB[y, l] = Ey^[y, l] for l <= K (T1[y, 0] = 0), the block at the torus origin."""
+    B = 2
+    _say(f"row pass alone H={H} W={W} M={M} N={N} K={K}")
+    plan = gfc.Plan(H, W, M, N, params={"low_bins": K}, tuned=False).build()
+    NH = N // 2 + 1
+    NHP = (NH + 31) // 32 * 32
+    KP = (K + 1 + 7) // 8 * 8
+    gx, gy = _fields(H + W, B, H, W)
+    tx, ty = torch.from_numpy(gx).cuda(), torch.from_numpy(gy).cuda()
+    u = torch.empty_like(tx)
+    ws = torch.zeros(plan.workspace_size(B), dtype=torch.uint8, device="cuda")
+    _stage(plan, 1, tx, ty, u, B, ws)
+    torch.cuda.synchronize()
+    raw = ws.cpu().numpy()
+    t_bytes = B * (H + 1) * NHP * 8
+    T = raw[:t_bytes].view(np.complex64).reshape(B, H + 1, NHP)[:, :, :NH].astype(np.complex128)
+    s0 = _align256(t_bytes)
+    SB = raw[s0:s0 + B * H * KP * 8].view(np.complex64).reshape(B, H, KP)[:, :, :K + 1]
+    l = np.arange(NH)
+    one_minus_w = 1.0 - np.exp(-2j * np.pi * l / N)
+    for b in range(B):
+        L = O.divergence(gx[b], gy[b], M, N, 0, 0)[:H + 1]
+        Lh = np.fft.fft(L, axis=1)[:, :NH]
+        Ex = np.zeros((H + 1, N))
+        Ex[:H, :W] = gx[b]
+        Ey = np.zeros((H, N))
+        Ey[:, :W] = gy[b]
+        want = Lh.copy()
+        want[:, :K + 1] = (np.fft.fft(Ex, axis=1)[:, :NH] * one_minus_w)[:, :K + 1]
+        e1 = _rel(T[b], want)
+        e2 = _rel(SB[b].astype(np.complex128), np.fft.fft(Ey, axis=1)[:, :K + 1])
+        _say(f"  image {b}: T1 rel {e1:.2e}, SB rel {e2:.2e}")
+        assert e1 <= TOL and e2 <= TOL, (b, e1, e2)
+
+
+@pytest.mark.parametrize("H,W,M,N", [(33, 70, 35, 72), (129, 200, 260, 400),
+                                     (801, 1200, 1620, 2400)])
+def test_inverse_row_pass_alone(H, W, M, N):
+    """Inverse row pass (row C2R of eq. (23), real part, crop, Algorithm B's constant) on a
+    given spectrum: u[y, x] = sum_l T2[y, l] w^(-l x) over the Hermitian extension (no
+    1/N: the column pass folds it in), x < W, minus the sum of the column partials."""
+    B = 2
+    _say(f"inverse row pass alone H={H} W={W} M={M} N={N}")
+    plan = gfc.Plan(H, W, M, N, tuned=False).build()
+    NH = N // 2 + 1
+    NHP = (NH + 31) // 32 * 32
+    K = plan.get_param("low_bins")
+    KP = (K + 1 + 7) // 8 * 8
+    Kb = plan.get_param("low_bins_b")
+    KbP = (Kb + 1 + 31) // 32 * 32
+    C = plan.get_param("col_c")
+    ntiles = (NH + C - 1) // C
+    rng = np.random.default_rng(H * W)
+    T2 = (rng.normal(size=(B, H + 1, NHP)) + 1j * rng.normal(size=(B, H + 1, NHP))) / N
+    T2[:, :, 0] = T2[:, :, 0].real  # a real row has real DC and Nyquist bins
+    if N % 2 == 0:
+        T2[:, :, N // 2] = T2[:, :, N // 2].real
+    T2 = T2.astype(np.complex64)
+    part = rng.normal(size=(B, ntiles))
+    ws = torch.zeros(plan.workspace_size(B), dtype=torch.uint8, device="cuda")
+    raw = np.zeros(ws.numel(), np.uint8)
+    t_bytes = B * (H + 1) * NHP * 8
+    raw[:t_bytes] = T2.reshape(-1).view(np.uint8)
+    side = _align256(t_bytes)
+    red = side + _align256(max(B * H * KP * 8, B * H * KbP * 8))
+    raw[red:red + part.nbytes] = part.reshape(-1).view(np.uint8)
+    ws.copy_(torch.from_numpy(raw))
+    u = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    dummy = torch.empty(1, device="cuda")
+    _stage(plan, 3, dummy, dummy, u, B, ws)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    for b in range(B):
+        v = np.fft.irfft(T2[b, :H, :NH].astype(np.complex128), n=N, axis=1) * N
+        want = v[:, :W] - part[b].sum()
+        e = _rel(got[b], want)
+        _say(f"  image {b}: rel {e:.2e}")
+        assert e <= TOL, (b, e)
