@@ -1,5 +1,5 @@
-"""Pass-level GPU checks: the forward row pass and the inverse row pass, each alone, through
-gfc_solve_batch_stage, against float64 numpy transforms of the same inputs. The intermediate
+"""Pass-level GPU checks: the forward row pass, the column pass and the inverse row pass, each
+alone, through gfc_solve_batch_stage, against float64 numpy transforms of the same inputs. The intermediate
 layout is the library's workspace (spectra T [B][H+1][NHP] complex64 from offset 0; the
 split side array SB [B][H][KP] at the next 256-byte boundary; column partials after it), so
 these tests know that layout on purpose."""
@@ -145,3 +145,71 @@ def test_inverse_row_pass_alone(H, W, M, N):
         e = _rel(got[b], want)
         _say(f"  image {b}: rel {e:.2e}")
         assert e <= TOL, (b, e)
+
+
+@pytest.mark.parametrize("H,W,M,N", [(33, 70, 35, 72), (129, 200, 260, 400),
+                                     (100, 37, 210, 80), (801, 1200, 1620, 2400)])
+def test_column_pass_alone(H, W, M, N):
+    """Column pass (the column slices of G^ of eq. (22) applied per row frequency l, the
+    reference term of Algorithm B) on given row spectra T1 [H+1] and side array SB [H]:
+    for every l the column input is T1[., l] plus the y-difference of SB[., l] (l <= K),
+    zero-extended to M rows; T2[y, l] = IDFT_M(G^(., l) DFT_M(column))[y] / N for y < H
+    (column 0 up to a constant that cancels), and the column partials sum to v at the grid
+    corner (r0, c0) of the block at the origin."""
+    B = 2
+    _say(f"column pass alone H={H} W={W} M={M} N={N}")
+    plan = gfc.Plan(H, W, M, N, tuned=False).build()
+    NH = N // 2 + 1
+    NHP = (NH + 31) // 32 * 32
+    K = plan.get_param("low_bins")
+    KP = (K + 1 + 7) // 8 * 8
+    Kb = plan.get_param("low_bins_b")
+    KbP = (Kb + 1 + 31) // 32 * 32
+    C = plan.get_param("col_c")
+    ntiles = (NH + C - 1) // C
+    oy, ox = O.block_offset(H, W, M, N)
+    r0, c0 = M - oy, N - ox
+    rng = np.random.default_rng(7 * H + W)
+    T1 = rng.normal(size=(B, H + 1, NHP)) + 1j * rng.normal(size=(B, H + 1, NHP))
+    T1[:, :, 0] = 0.0  # the row pass's split form leaves (1 - w^0) Ex^ = 0
+    T1[:, :, N // 2] = T1[:, :, N // 2].real  # real rows: real Nyquist bin
+    SB = rng.normal(size=(B, H, KP)) + 1j * rng.normal(size=(B, H, KP))
+    SB[:, :, 0] = SB[:, :, 0].real
+    T1 = T1.astype(np.complex64)
+    SB = SB.astype(np.complex64)
+    raw = np.zeros(plan.workspace_size(B), np.uint8)
+    t_bytes = B * (H + 1) * NHP * 8
+    raw[:t_bytes] = T1.reshape(-1).view(np.uint8)
+    side = _align256(t_bytes)
+    raw[side:side + SB.nbytes] = SB.reshape(-1).view(np.uint8)
+    red = side + _align256(max(B * H * KP * 8, B * H * KbP * 8))
+    ws = torch.from_numpy(raw).cuda()
+    dummy = torch.empty(1, device="cuda")
+    _stage(plan, 2, dummy, dummy, dummy, B, ws)
+    torch.cuda.synchronize()
+    out = ws.cpu().numpy()
+    T2 = out[:t_bytes].view(np.complex64).reshape(B, H + 1, NHP)
+    part = out[red:red + B * ntiles * 8].view(np.float64).reshape(B, ntiles)
+    G = O.green_spectrum(M, N)[:, :NH]
+    for b in range(B):
+        col = np.zeros((M, NH), np.complex128)
+        col[:H + 1] = T1[b, :, :NH]
+        d = np.zeros((M, K + 1), np.complex128)
+        d[:H] += SB[b, :, :K + 1]
+        d[1:H + 1] -= SB[b, :, :K + 1]
+        col[:, :K + 1] += d
+        v = np.fft.ifft(G * np.fft.fft(col, axis=0), axis=0) / N
+        got = T2[b, :H, :NH].astype(np.complex128)
+        # column 0 (the pseudo-inverse, G^(0, 0) = 0) is fixed only up to a constant c: it
+        # adds c to every pixel and to the corner alike, and the corner subtraction of
+        # Algorithm B removes it; the pass may pick any c, the same in both places
+        c = np.mean(got[:, 0] - v[:H, 0])
+        v[:, 0] += c
+        e = _rel(got, v[:H])
+        row = np.fft.irfft(v[r0 % M], n=N) * N  # v on the corner's row, with c
+        corner = row[c0 % N]
+        ec = abs(part[b].sum() - corner) / np.abs(row).max()
+        _say(f"  image {b}: T2 rel {e:.2e}, corner {part[b].sum():.6e} vs {corner:.6e} "
+             f"(column-0 constant {c.real:.3e})")
+        assert e <= TOL, (b, e)
+        assert ec <= TOL, (b, ec)
