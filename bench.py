@@ -24,7 +24,9 @@ HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 FP32_VALU_PEAK = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, packed FP32 off
 METRIC = "solves/s at 801x1200 B=100 FP32; fwd+bwd & ragged vs plain; % peak HBM BW"
 KERNEL_SOURCES = ["paper_1902_00176_amd/csrc/gfc_row.h", "paper_1902_00176_amd/csrc/gfc_col.hip",
-                  "paper_1902_00176_amd/csrc/gfc_dft.h", "paper_1902_00176_amd/csrc/gfc_internal.h"]
+                  "paper_1902_00176_amd/csrc/gfc_dft.h", "paper_1902_00176_amd/csrc/gfc_internal.h",
+                  "paper_1902_00176_amd/csrc/gfc_buf.h", "paper_1902_00176_amd/csrc/gfc_edit.h",
+                  "paper_1902_00176_amd/csrc/gfc_plan.h"]
 
 
 def kernel_source_hash() -> str:
