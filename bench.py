@@ -26,7 +26,7 @@ METRIC = "solves/s at 801x1200 B=100 FP32; fwd+bwd & ragged vs plain; % peak HBM
 KERNEL_SOURCES = ["paper_1902_00176_amd/csrc/gfc_row.h", "paper_1902_00176_amd/csrc/gfc_col.hip",
                   "paper_1902_00176_amd/csrc/gfc_dft.h", "paper_1902_00176_amd/csrc/gfc_internal.h",
                   "paper_1902_00176_amd/csrc/gfc_buf.h", "paper_1902_00176_amd/csrc/gfc_edit.h",
-                  "paper_1902_00176_amd/csrc/gfc_plan.h"]
+                  "paper_1902_00176_amd/csrc/gfc_plan.h", "paper_1902_00176_amd/csrc/gfc_twiddle.h"]
 
 
 def kernel_source_hash() -> str:

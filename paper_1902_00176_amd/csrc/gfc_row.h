@@ -14,6 +14,7 @@
 #include "gfc_dft.h"
 #include "gfc_edit.h"
 #include "gfc_internal.h"
+#include "gfc_twiddle.h"
 
 #include <utility>
 
@@ -74,17 +75,13 @@ __device__ __forceinline__ int fresh_zero() {
 
 // Forward four-step body. On entry lane j < N2 holds a[y1] = z[N2*y1 + j]; on exit the
 // spectrum Z is in LDS (re/im planes) in natural order.
-template <int N1, int N2>
+template <int N1, int N2, bool EXACT_TW = false>
 __device__ __forceinline__ void fwd_fft_to_lds(cx (&a)[N1], float* re, float* im, int lane,
                                                rsrc_t twA, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N2) {
     DftSel<N1, -1>::run(a);
-#pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) {
-      const f2b w = bld2(twA, lane * 8, tz + k1 * N2 * 8);
-      a[k1] = cmul(a[k1], cx{w.x, w.y});
-    }
+    twiddles<N1, N2, EXACT_TW>(twA, lane, tz, [&](int k1, cx w) { a[k1] = cmul(a[k1], w); });
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) {
       re[k1 * C::SA + lane] = a[k1].x;
@@ -117,11 +114,7 @@ __device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], floa
   using C = RowCfg<N1, N2>;
   if (lane < N1) {
     DftSel<N2, +1>::run(b);
-#pragma unroll
-    for (int j2 = 1; j2 < N2; ++j2) {
-      const f2b w = bld2(twB, lane * 8, tz + j2 * N1 * 8);
-      b[j2] = cmulconj(b[j2], cx{w.x, w.y});
-    }
+    twiddles<N2, N1>(twB, lane, tz, [&](int j2, cx w) { b[j2] = cmulconj(b[j2], w); });
 #pragma unroll
     for (int j2 = 0; j2 < N2; ++j2) {
       re[j2 * C::SB + lane] = b[j2].x;
@@ -583,7 +576,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     slot_sync();
     }  // !FULLBINS
 
-    fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
+    fwd_fft_to_lds<N1, N2, FULLBINS>(a, re, im, lane, rtw, tz);
 
     // Z = FFT(L[y0] + i L[y0+1]): L^[y0, l] = (Z[l] + conj Z[N-l]) / 2,
     // L^[y0+1, l] = (Z[l] - conj Z[N-l]) / 2i; bins l <= K come from the direct sums

@@ -7,6 +7,7 @@
 #include "gfc_buf.h"
 #include "gfc_dft.h"
 #include "gfc_internal.h"
+#include "gfc_twiddle.h"
 
 namespace gfc {
 
@@ -59,11 +60,11 @@ k_zfft(ZfftArgs a) {
   __syncthreads();
   if (j < P2) {
     DftSel<P1, SIGN>::run(x);
-#pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) {
-      const f2b w = bld2(rtw, j * 8, k1 * P2 * 8);  // w_P^(k1 j), forward sign
-      x[k1] = SIGN < 0 ? cmul(x[k1], cx{w.x, w.y}) : cmulconj(x[k1], cx{w.x, w.y});
-    }
+    // w_P^(k1 j), forward sign (conjugated for the inverse); the forward transform runs on
+    // the divergence, whose lowest frequencies the solve amplifies: exact table twiddles
+    twiddles<P1, P2, (SIGN < 0)>(rtw, j, 0, [&](int k1, cx w) {
+      x[k1] = SIGN < 0 ? cmul(x[k1], w) : cmulconj(x[k1], w);
+    });
 #pragma unroll
     for (int k1 = 0; k1 < P1; ++k1) {
       re[k1 * C::SA + j] = x[k1].x;
