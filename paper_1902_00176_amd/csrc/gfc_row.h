@@ -406,6 +406,28 @@ __device__ __forceinline__ void pair_load(cx (&a)[N1], cx (&ax0)[kLowBins],
   }
 }
 
+// Lane factors of the low-bin sums: Ey bins l = 1..K times w_N^(l j) = wp[l]; Ex bins times
+// (1 - w_N^l) w_N^(l j), with 1 - w_N^l = 2 sin^2(pi l / N) + i sin(2 pi l / N) folded in as
+// compile-time constants (float64-built, rounded once).
+template <int N, int... L>
+__device__ __forceinline__ void low_lane_factors(cx (&ax0)[kLowBins], cx (&ax1)[kLowBins],
+                                                 cx (&ay0)[kLowBins + 1],
+                                                 cx (&ay1)[kLowBins + 1],
+                                                 const cx (&wp)[kLowBins + 1],
+                                                 std::integer_sequence<int, L...>) {
+  auto one = [&](auto lc) {
+    constexpr int l = decltype(lc)::value + 1;
+    constexpr double h = detail::cs2pi(l, 2 * N, 1);  // sin(pi l / N)
+    constexpr cx om = {float(2.0 * h * h), float(detail::cs2pi(l, N, 1))};
+    const cx wx = cmul(om, wp[l]);
+    ax0[l - 1] = cmul(ax0[l - 1], wx);
+    ax1[l - 1] = cmul(ax1[l - 1], wx);
+    ay0[l] = cmul(ay0[l], wp[l]);
+    ay1[l] = cmul(ay1[l], wp[l]);
+  };
+  (one(std::integral_constant<int, L>{}), ...);
+}
+
 // LDS floats of one slot's plane in the forward row pass: the FFT exchange, or the low-bin
 // lane sums (4 (2K + 1) values over G + 1 lanes) when larger
 template <int N1, int N2>
@@ -541,17 +563,17 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     constexpr int NVL = FULLBINS ? 0 : (NV + C::G - 1) / C::G;
     float lowsum[NVL > 0 ? NVL : 1];
     if constexpr (!FULLBINS) {
-#pragma unroll
-    for (int l = 0; l <= KL; ++l) {
-      const f2b wy = bld2(rtl, lane * 8, tz + (KL + 1 + l) * C::G * 8);
-      if (l > 0) {
-        const f2b wx = bld2(rtl, lane * 8, tz + l * C::G * 8);
-        ax0[l - 1] = cmul(ax0[l - 1], cx{wx.x, wx.y});
-        ax1[l - 1] = cmul(ax1[l - 1], cx{wx.x, wx.y});
-        ay0[l] = cmul(ay0[l], cx{wy.x, wy.y});
-        ay1[l] = cmul(ay1[l], cx{wy.x, wy.y});
-      }
+    // w_N^(l j) = (w_N^j)^l from one table row (squarings and products: at most three
+    // float32 roundings), and the Ex factor 1 - w_N^l = 2 sin^2(pi l / N) + i sin(2 pi l / N)
+    // as float64-built compile-time constants: one load instead of 2K
+    cx wp[KL + 1];
+    {
+      const f2b w1 = bld2(rtl, lane * 8, tz + (KL + 2) * C::G * 8);
+      wp[1] = {w1.x, w1.y};
     }
+#pragma unroll
+    for (int l = 2; l <= KL; ++l) wp[l] = (l % 2 == 0) ? cmul(wp[l / 2], wp[l / 2]) : cmul(wp[l - 1], wp[1]);
+    low_lane_factors<C::N>(ax0, ax1, ay0, ay1, wp, std::make_integer_sequence<int, KL>{});
     // value index: row r of the pair, complex index c < NC (Ex bins 1..K, then Ey bins 0..K)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
