@@ -1,5 +1,6 @@
-"""Pass-level GPU checks: the forward row pass, the column pass and the inverse row pass, each
-alone, through gfc_solve_batch_stage, against float64 numpy transforms of the same inputs. The intermediate
+"""Pass-level GPU checks: the forward row pass, the column pass and the inverse row pass, and
+the first and last backward passes, each alone, through gfc_solve_batch_stage and
+gfc_solve_backward_stage, against float64 numpy transforms of the same inputs. The intermediate
 layout is the library's workspace (spectra T [B][H+1][NHP] complex64 from offset 0; the
 split side array SB [B][H][KP] at the next 256-byte boundary; column partials after it), so
 these tests know that layout on purpose."""
@@ -213,3 +214,107 @@ def test_column_pass_alone(H, W, M, N):
              f"(column-0 constant {c.real:.3e})")
         assert e <= TOL, (b, e)
         assert ec <= TOL, (b, ec)
+
+
+def _bstage(plan, k, du, dgx, dgy, B, ws):
+    st = torch.cuda.current_stream()
+    r = gfc.lib().gfc_solve_backward_stage(plan.handle, k, du.data_ptr(), dgx.data_ptr(),
+                                           dgy.data_ptr(), B, ws.data_ptr(), ws.numel(),
+                                           ctypes.c_void_p(st.cuda_stream))
+    assert r == 0, gfc.lib().gfc_status_str(r)
+
+
+@pytest.mark.parametrize("H,W,M,N", [(33, 70, 35, 72), (129, 200, 260, 400),
+                                     (801, 1200, 1620, 2400)])
+def test_backward_row_pass_alone(H, W, M, N):
+    """First backward pass (the adjoint of the inverse row pass): U[y, l] = the row DFT of
+    du (forward sign) for y < H, and partial sums whose total is sum(du), the weight of the
+    adjoint of Algorithm B's corner subtraction."""
+    B = 2
+    _say(f"backward row pass alone H={H} W={W} M={M} N={N}")
+    plan = gfc.Plan(H, W, M, N, tuned=False).build()
+    NH = N // 2 + 1
+    NHP = (NH + 31) // 32 * 32
+    K = plan.get_param("low_bins")
+    KP = (K + 1 + 7) // 8 * 8
+    Kb = plan.get_param("low_bins_b")
+    KbP = (Kb + 1 + 31) // 32 * 32
+    du = np.random.default_rng(H + W).normal(size=(B, H, W)).astype(np.float32)
+    tdu = torch.from_numpy(du).cuda()
+    ws = torch.zeros(plan.workspace_size(B), dtype=torch.uint8, device="cuda")
+    dummy = torch.empty(1, device="cuda")
+    _bstage(plan, 1, tdu, dummy, dummy, B, ws)
+    torch.cuda.synchronize()
+    raw = ws.cpu().numpy()
+    t_bytes = B * (H + 1) * NHP * 8
+    U = raw[:t_bytes].view(np.complex64).reshape(B, H + 1, NHP)
+    red = _align256(t_bytes) + _align256(max(B * H * KP * 8, B * H * KbP * 8))
+    sums = raw[red:red + (len(raw) - red) // 8 * 8].view(np.float64)
+    for b in range(B):
+        want = np.fft.fft(np.pad(du[b].astype(np.float64), ((0, 0), (0, N - W))), axis=1)[:, :NH]
+        e = _rel(U[b, :H, :NH].astype(np.complex128), want)
+        _say(f"  image {b}: U rel {e:.2e}")
+        assert e <= TOL, (b, e)
+    # the reduction region starts with the partial sums, [B][nsums]; nsums (row blocks per
+    # image) depends on the FFT slot width, so it is found as the split that gives every
+    # image its own total (the rest of the zero-filled region adds nothing)
+    tot = du.astype(np.float64).sum(axis=(1, 2))
+    assert np.isclose(sums.sum(), tot.sum(), rtol=1e-6, atol=1e-6 * np.abs(du).sum())
+    found = False
+    for nsums in range(1, len(sums) // B + 1):
+        s = sums[:B * nsums].reshape(B, nsums).sum(axis=1)
+        if np.allclose(s, tot, rtol=1e-6, atol=1e-6 * np.abs(du).sum()):
+            found = True
+            break
+    assert found, "no prefix of the reduction region sums to sum(du) per image"
+
+
+@pytest.mark.parametrize("H,W,M,N", [(33, 70, 35, 72), (129, 200, 260, 400),
+                                     (801, 1200, 1620, 2400)])
+def test_backward_inverse_row_pass_alone(H, W, M, N):
+    """Last backward pass on given W [H+1] and SD [H] (l <= Kb): dgx[y] = C2R of
+    (1 - w^(-l)) W[y, l] (-D_x as its symbol, forward differences), dgy[y] = C2R of SD[y, l]
+    for l <= Kb and of W[y, l] - W[y+1, l] above (-D_y), both unnormalised, x < W."""
+    B = 2
+    _say(f"backward inverse row pass alone H={H} W={W} M={M} N={N}")
+    plan = gfc.Plan(H, W, M, N, tuned=False).build()
+    NH = N // 2 + 1
+    NHP = (NH + 31) // 32 * 32
+    K = plan.get_param("low_bins")
+    KP = (K + 1 + 7) // 8 * 8
+    Kb = plan.get_param("low_bins_b")
+    KbP = (Kb + 1 + 31) // 32 * 32
+    rng = np.random.default_rng(3 * H + W)
+    Wv = (rng.normal(size=(B, H + 1, NHP)) + 1j * rng.normal(size=(B, H + 1, NHP))) / N
+    Wv[:, :, 0] = Wv[:, :, 0].real
+    Wv[:, :, N // 2] = Wv[:, :, N // 2].real
+    SD = (rng.normal(size=(B, H, KbP)) + 1j * rng.normal(size=(B, H, KbP))) / N
+    SD[:, :, 0] = SD[:, :, 0].real
+    if Kb == N // 2:
+        SD[:, :, Kb] = SD[:, :, Kb].real
+    Wv = Wv.astype(np.complex64)
+    SD = SD.astype(np.complex64)
+    raw = np.zeros(plan.workspace_size(B), np.uint8)
+    t_bytes = B * (H + 1) * NHP * 8
+    raw[:t_bytes] = Wv.reshape(-1).view(np.uint8)
+    side = _align256(t_bytes)
+    raw[side:side + SD.nbytes] = SD.reshape(-1).view(np.uint8)
+    ws = torch.from_numpy(raw).cuda()
+    dgx = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    dgy = torch.empty_like(dgx)
+    dummy = torch.empty(1, device="cuda")
+    _bstage(plan, 3, dummy, dgx, dgy, B, ws)
+    torch.cuda.synchronize()
+    l = np.arange(NH)
+    sym = 1.0 - np.exp(2j * np.pi * l / N)
+    for b in range(B):
+        Wb = Wv[b, :, :NH].astype(np.complex128)
+        X1 = sym * Wb[:H]
+        X2 = Wb[:H] - Wb[1:H + 1]
+        X2[:, :Kb + 1] = SD[b, :, :Kb + 1]
+        wx = np.fft.irfft(X1, n=N, axis=1)[:, :W] * N
+        wy = np.fft.irfft(X2, n=N, axis=1)[:, :W] * N
+        ex = _rel(dgx[b].cpu().numpy(), wx)
+        ey = _rel(dgy[b].cpu().numpy(), wy)
+        _say(f"  image {b}: dgx rel {ex:.2e}, dgy rel {ey:.2e}")
+        assert ex <= TOL and ey <= TOL, (b, ex, ey)
