@@ -267,14 +267,16 @@ const char* gfc_status_str(gfc_status s);
  * spectrum is 1/lambda with lambda = -4 sin^2(pi kz/P) - 4 sin^2(pi ky/M) - 4 sin^2(pi kx/N),
  * the 7-point stencil's symbol, and 0 at the DC bin). A D x H x W volume sits centred in a
  * P x M x N torus (P = 0: the smallest even 2/3/5-smooth P >= 2D, likewise M, N);
- * u = v[block] - v[0,0,0]. P, M and N are at most 512 (GFC_E_SIZE otherwise): the 7-point
- * divergence is transformed in float32 as it stands, with no split of the lowest
- * frequencies, and the rounding of those bins grows with the square of the longest extent.
+ * u = v[block] - v[0,0,0]. P is at most 512 and N a supported row length (GFC_E_SIZE
+ * otherwise); M and N follow gfc_plan_create's rules.
  *   gx, gy, gz : [B][D][H][W] float32 forward-difference fields, zero exterior
  *   u          : [B][D][H][W] float32
- * Passes: rows of the 7-point divergence (x), a complex FFT along z, the column recursion
- * along y per (kz, l), the inverse z FFT, the inverse rows with crop and constant. Forward
- * only. Errors and conventions as for the two-dimensional entry points.
+ * Passes: rows of the 7-point divergence (x), whose 5 lowest row frequencies are kept as
+ * the x-, y- and z-parts apart (direct sums of Ex, Ey, Ez); complex FFTs along z; the z
+ * difference applied as its symbol to those bins; the column recursion along y per
+ * (kz, l) with the y difference inside it; the inverse z FFT; the inverse rows with crop
+ * and constant. Forward only. Errors and conventions as for the two-dimensional entry
+ * points.
  */
 typedef struct gfc_plan3_s* gfc_plan3_t;
 gfc_status gfc_plan3_create(gfc_plan3_t* out, int D, int H, int W, int P, int M, int N,

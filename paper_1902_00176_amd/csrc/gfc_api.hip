@@ -622,7 +622,6 @@ void gfc_plan_destroy(gfc_plan_t p) {
 
 }  // extern "C"
 
-constexpr int kMaxVolumeExtent = 512;
 
 struct gfc_plan3_s {
   gfc_plan_s* p2 = nullptr;  // the (y, x) part: H, W, M, N, row kernels, column geometry
@@ -632,19 +631,22 @@ struct gfc_plan3_s {
   void* dmem = nullptr;
   gfc::ColConst* cc = nullptr;  // [P][NH]
   gfc::f2* tw = nullptr;        // [P1][P2]
+  gfc::f2* omz = nullptr;       // [P]: 1 - w_P^kz, the z difference as its symbol
 };
 
 namespace {
 struct Ws3 {
-  size_t t, side, red, tot, total;  // tot: one corner-constant sum per volume
+  size_t t, side, sz, red, tot, total;  // side: SB, sz: SZ; tot: corner sums per volume
 };
 Ws3 ws3_layout(const gfc_plan3_s* q, int B) {
   const gfc_plan_s* p = q->p2;
   Ws3 w{};
   const size_t vols = size_t(B) * q->P;
+  const size_t side = align256(vols * size_t(p->H) * p->KP * sizeof(f2));
   w.t = 0;
   w.side = align256(vols * size_t(p->H + 1) * p->NHP * sizeof(f2));
-  w.red = w.side + align256(vols * size_t(p->H) * p->KP * sizeof(f2));
+  w.sz = w.side + side;
+  w.red = w.sz + side;
   w.tot = w.red + align256(vols * size_t(p->ntiles_f) * sizeof(double));
   w.total = w.tot + align256(size_t(B) * sizeof(double));
   return w;
@@ -665,21 +667,15 @@ gfc_status gfc_plan3_create(gfc_plan3_t* out, int D, int H, int W, int P, int M,
   gfc_plan_t p2 = nullptr;
   const gfc_status st = gfc_plan_create(&p2, H, W, M, N, flags);
   if (st != GFC_OK) return st;
-  // Volumes transform the literal 7-point divergence in float32: there is no split of the
-  // lowest frequencies into their x-, y- and z-parts as for images, and the rounding of the
-  // lowest bins grows with the square of the longest torus extent. Up to 512 along every
-  // axis the error stays a few 1e-6; longer axes are refused.
-  if (P > kMaxVolumeExtent || p2->M > kMaxVolumeExtent || p2->N > kMaxVolumeExtent) {
-    gfc_plan_destroy(p2);
-    return GFC_E_SIZE;
-  }
   // a volume's (P planes) spectra must stay addressable with 32-bit offsets per plane set
   if ((long long)P * (p2->H + 1) * p2->NHP * 8 >= (1LL << 31) ||
       (long long)D * H * W * 4 >= (1LL << 30)) {
     gfc_plan_destroy(p2);
     return GFC_E_SIZE;
   }
-  p2->K = 0;  // only the DC column (kz, l) = (0, 0) takes the split input
+  // the row bins l <= kLowBins take the split input (x-, y- and z-parts apart); the plane
+  // extension for thin tori is for images only
+  p2->K = kLowBins;
   derive_geometry(p2);
   auto* q = new (std::nothrow) gfc_plan3_s;
   if (!q) {
@@ -718,12 +714,22 @@ gfc_status gfc_green_build3(gfc_plan3_t q, void* stream) {
       cs2pi(long(k1) * j, P, c, s);
       tw[size_t(k1) * P2 + j] = f2{float(c), float(-s)};
     }
+  // 1 - w_P^kz = 2 sin^2(pi kz / P) + i sin(2 pi kz / P)
+  std::vector<f2> omz(P);
+  for (int kz = 0; kz < P; ++kz) {
+    const double h = std::sin(kPi * double(kz) / double(P));
+    double c, sn;
+    cs2pi(kz, P, c, sn);
+    omz[kz] = f2{float(2.0 * h * h), float(sn)};
+  }
   const size_t o_cc = 0;
   const size_t o_tw = align256(cc.size() * sizeof(ColConst));
-  const size_t total = o_tw + align256(tw.size() * sizeof(f2));
+  const size_t o_omz = o_tw + align256(tw.size() * sizeof(f2));
+  const size_t total = o_omz + align256(omz.size() * sizeof(f2));
   std::vector<unsigned char> host(total, 0);
   std::memcpy(host.data() + o_cc, cc.data(), cc.size() * sizeof(ColConst));
   std::memcpy(host.data() + o_tw, tw.data(), tw.size() * sizeof(f2));
+  std::memcpy(host.data() + o_omz, omz.data(), omz.size() * sizeof(f2));
   void* d = nullptr;
   if (hipMalloc(&d, total) != hipSuccess) return GFC_E_OOM;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -735,6 +741,7 @@ gfc_status gfc_green_build3(gfc_plan3_t q, void* stream) {
   q->dmem = d;
   q->cc = reinterpret_cast<ColConst*>(static_cast<unsigned char*>(d) + o_cc);
   q->tw = reinterpret_cast<f2*>(static_cast<unsigned char*>(d) + o_tw);
+  q->omz = reinterpret_cast<f2*>(static_cast<unsigned char*>(d) + o_omz);
   q->built = true;
   return GFC_OK;
 }
@@ -757,19 +764,23 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   auto* ws = static_cast<unsigned char*>(workspace);
   f2* T = reinterpret_cast<f2*>(ws + w.t);
   f2* SB = reinterpret_cast<f2*>(ws + w.side);
+  f2* SZ = reinterpret_cast<f2*>(ws + w.sz);
   double* partial = reinterpret_cast<double*>(ws + w.red);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int D = q->D, P = q->P;
   const long long plane = (long long)(p->H + 1) * p->NHP;
-  // 1. rows of the 7-point divergence, every slice z in [0, D] of every volume
+  const long long splane = (long long)p->H * p->KP;
+  // 1. rows of the 7-point divergence, every slice z in [0, D] of every volume; bins
+  //    l <= K split: T gets (1 - w_N^l) Ex^, SB gets Ey^ and SZ gets Ez^ of planes z < D
   RowFwdArgs f = row_fwd_args(p, gx, gy, T, SB);
   f.edit = kIn3D;
   f.gz = gz;
   f.zd = D;
   f.zp = P;
+  f.SZ = SZ;
   gfc_status st = hip_status(p->rk->fwd(f, B * (D + 1), s));
   if (st != GFC_OK) return st;
-  // 2. z transform: D + 1 planes in, P planes out
+  // 2. z transforms: T with D + 1 planes in, the side arrays with D, P planes out each
   ZfftArgs z{};
   z.T = T;
   z.tw = q->tw;
@@ -782,9 +793,22 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   z.dout = P;
   st = hip_status(q->zk->run(z, -1, B, s));
   if (st != GFC_OK) return st;
-  // 3. the DC column's running sums; 4. the column pass per (kz, l)
-  st = hip_status(launch_sb_volume(T, SB, p->H, p->KP, P, p->NHP, plane * P,
-                                   (long long)p->H * p->KP, B, s));
+  ZfftArgs zs = z;
+  zs.R = p->H;
+  zs.NH = p->K + 1;
+  zs.NHP = p->KP;
+  zs.plane = splane;
+  zs.vol_stride = splane * P;
+  zs.din = D;
+  zs.T = SB;
+  st = hip_status(q->zk->run(zs, -1, B, s));
+  if (st != GFC_OK) return st;
+  zs.T = SZ;
+  st = hip_status(q->zk->run(zs, -1, B, s));
+  if (st != GFC_OK) return st;
+  // 3. the z difference of Ez as its symbol into the split bins; 4. the column pass
+  st = hip_status(launch_sz_combine(T, SZ, q->omz, p->H, p->NHP, p->K, p->KP, P, plane,
+                                    splane, B, s));
   if (st != GFC_OK) return st;
   ColFwdArgs c = col_fwd_args(p, T, SB, partial);
   c.cc = q->cc;

@@ -108,51 +108,32 @@ hipError_t launch_sb_prefix(f2* SB, int H, int KP, long long img_sb, int B, hipS
 
 namespace gfc {
 
-// Volumes: the split side array of the column pass after the z transform. Only the column
-// (kz, l) = (0, 0) has the pseudo-inverse path, which takes the running sum b of its input
-// c = T[vol][0][y][0] over the rows; every other plane gets b = 0, so (1 - S) b adds nothing.
+// Volumes: the split bins l <= K of the column input are a = (1 - w_N^l) Ex^ + (1 - w_P^kz) Ez^
+// and b = Ey^ (the y difference is applied inside the column recursion). T holds the z
+// transform of (1 - w_N^l) Ex^ for those bins; here the z difference of Ez is added as its
+// symbol, one thread per (y, l).
 __global__ void __launch_bounds__(kScanThreads)
-k_sb_volume(const f2* T, f2* SB, int H, int KP, int P, int NHP, long long vol_stride,
-            long long img_sb) {
-  __shared__ double sx[kScanThreads], sy[kScanThreads];
-  const int t = threadIdx.x;
-  const int vol = blockIdx.x / P, kz = blockIdx.x % P;
-  f2* out = SB + (long long)blockIdx.x * img_sb;
-  if (kz != 0) {
-    for (int y = t; y < H; y += kScanThreads) out[(long long)y * KP] = f2{0.f, 0.f};
-    return;
-  }
-  const f2* in = T + vol * vol_stride;  // plane 0 of the volume, column l = 0 of each row
-  double cx = 0.0, cy = 0.0;
-  for (int y0 = 0; y0 < H; y0 += kScanThreads) {
-    const int y = y0 + t;
-    double vx = 0.0, vy = 0.0;
-    if (y < H) {
-      const f2 v = in[(long long)y * NHP];
-      vx = v.x;
-      vy = v.y;
-    }
-    sx[t] = vx;
-    sy[t] = vy;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-      const double ax = t >= d ? sx[t - d] : 0.0, ay = t >= d ? sy[t - d] : 0.0;
-      __syncthreads();
-      sx[t] += ax;
-      sy[t] += ay;
-      __syncthreads();
-    }
-    if (y < H) out[(long long)y * KP] = f2{float(cx + sx[t]), float(cy + sy[t])};
-    cx += sx[kScanThreads - 1];
-    cy += sy[kScanThreads - 1];
-    __syncthreads();
-  }
+k_sz_combine(f2* T, const f2* SZ, const f2* omz, int H, int NHP, int K, int KP, int P,
+             long long plane_t, long long plane_s) {
+  const int pl = blockIdx.y;  // volume * P + kz
+  const int kz = pl % P;
+  const int i = blockIdx.x * kScanThreads + threadIdx.x;
+  const int K1 = K + 1;
+  if (i >= H * K1) return;
+  const int y = i / K1, l = i % K1;
+  const f2 o = omz[kz];
+  const f2 z = SZ[pl * plane_s + (long long)y * KP + l];
+  f2& t = T[pl * plane_t + (long long)y * NHP + l];
+  t.x += o.x * z.x - o.y * z.y;
+  t.y += o.x * z.y + o.y * z.x;
 }
 
-hipError_t launch_sb_volume(const f2* T, f2* SB, int H, int KP, int P, int NHP,
-                            long long vol_stride, long long img_sb, int B, hipStream_t s) {
-  hipLaunchKernelGGL(k_sb_volume, dim3(B * P), dim3(kScanThreads), 0, s, T, SB, H, KP, P, NHP,
-                     vol_stride, img_sb);
+hipError_t launch_sz_combine(f2* T, const f2* SZ, const f2* omz, int H, int NHP, int K, int KP,
+                             int P, long long plane_t, long long plane_s, int B, hipStream_t s) {
+  if (K < 0 || K >= KP || H < 1) return hipErrorInvalidValue;
+  const int n = H * (K + 1);
+  hipLaunchKernelGGL(k_sz_combine, dim3((n + kScanThreads - 1) / kScanThreads, B * P),
+                     dim3(kScanThreads), 0, s, T, SZ, omz, H, NHP, K, KP, P, plane_t, plane_s);
   return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct RowFwdArgs {
   // gy, gz are [B][zd][H][W]; T1 planes are [B][zp][H+1][NHP] (plane z of each volume)
   const float* gz;
   int zd, zp;
+  f2* SZ;             // volumes: [B][zp][H][KP] row sums of gz for bins l <= K (plane z < zd)
 };
 
 // Inverse row pass: rows y in [0, H) of T2 (already scaled by 1/N), two rows per complex
@@ -210,12 +211,14 @@ struct ZKernels {
   hipError_t (*run)(const ZfftArgs&, int sign, int B, hipStream_t);
 };
 const ZKernels* find_z_kernels(int P);
-// volumes: SB[vol * P + kz][y][0] = (kz == 0) ? sum_{y' <= y} T[vol][0][y'][0] : 0, y < H
 // total[b] = sum of partial[b][0 .. nparts) in a fixed order, one workgroup per volume
 hipError_t launch_partial_sums(const double* partial, int nparts, double* total, int B,
                                hipStream_t s);
-hipError_t launch_sb_volume(const f2* T, f2* SB, int H, int KP, int P, int NHP,
-                            long long vol_stride, long long img_sb, int B, hipStream_t s);
+// Volumes, after the z transforms of T and of the side array SZ (row sums of Ez): the split
+// bins take the z difference as its symbol, T[vol][kz][y][l] += (1 - w_P^kz) SZ[vol][kz][y][l]
+// for y < H, l <= K (omz[kz] = 1 - w_P^kz, float64-built).
+hipError_t launch_sz_combine(f2* T, const f2* SZ, const f2* omz, int H, int NHP, int K, int KP,
+                             int P, long long plane_t, long long plane_s, int B, hipStream_t s);
 
 // launchers (defined in the kernel files)
 struct RowKernels {

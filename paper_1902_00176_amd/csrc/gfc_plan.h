@@ -107,6 +107,7 @@ inline RowFwdArgs row_fwd_args(const gfc_plan_s* p, const float* gx, const float
   a.img_t1 = (long long)(p->H + 1) * p->NHP;
   a.img_sb = (long long)p->H * p->KP;
   a.gz = nullptr;
+  a.SZ = nullptr;
   a.zd = 0;
   a.zp = 1;
   return a;

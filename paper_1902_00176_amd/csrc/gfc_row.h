@@ -170,6 +170,14 @@ __device__ __forceinline__ void low_acc(cx (&ax)[kLowBins], cx (&ay)[kLowBins + 
   (acc_tw<N1, (L + 1) * Y1>(ay[L + 1], vy), ...);
 }
 
+// low-bin partial sums of one y1 for all bins l = 0..K of one field (volumes: Ez)
+template <int N1, int Y1, int... L>
+__device__ __forceinline__ void low_acc_all(cx (&az)[kLowBins + 1], float vz,
+                                            std::integer_sequence<int, L...>) {
+  acc_tw<N1, 0>(az[0], vz);
+  (acc_tw<N1, (L + 1) * Y1>(az[L + 1], vz), ...);
+}
+
 // Loads of one y1 column of a row pair and its low-bin sums (x = N2 y1 + lane):
 // L[y, x] = Ex[y, x] - Ex[y, x-1] + Ey[y, x] - Ey[y-1, x] for rows y0 and y0 + 1. Elements
 // outside the image (x >= W, x - 1 < 0, rows outside [0, H), lanes j >= N2) read 0 through
@@ -342,8 +350,21 @@ struct VolRowsU {
   rsrc_t x0, x1, ym, y0, y1, z0, z1, zm0, zm1;
   int vb;
 };
+// The low-bin sums of the split (bins l <= K) take Ex, Ey and Ez of plane z undifferenced.
+struct VolLow {
+  cx ax0[kLowBins], ay0[kLowBins + 1], az0[kLowBins + 1];
+  cx ax1[kLowBins], ay1[kLowBins + 1], az1[kLowBins + 1];
+};
+template <int N1, int Y1>
+__device__ __forceinline__ void vol_low(VolLow& w, float gx0, float gy0, float gz0, float gx1,
+                                        float gy1, float gz1) {
+  low_acc<N1, Y1>(w.ax0, w.ay0, gx0, gy0, std::make_integer_sequence<int, kLowBins>{});
+  low_acc<N1, Y1>(w.ax1, w.ay1, gx1, gy1, std::make_integer_sequence<int, kLowBins>{});
+  low_acc_all<N1, Y1>(w.az0, gz0, std::make_integer_sequence<int, kLowBins>{});
+  low_acc_all<N1, Y1>(w.az1, gz1, std::make_integer_sequence<int, kLowBins>{});
+}
 template <int N1, int N2, int Y1>
-__device__ __forceinline__ void vol_block(cx (&a)[N1], const VolRowsU& r, int W) {
+__device__ __forceinline__ void vol_block(cx (&a)[N1], VolLow& w, const VolRowsU& r, int W) {
   const int v = r.vb + N2 * Y1 * 4;
   const float gx0 = bld1(r.x0, v, 0), gx0m = bld1(r.x0, v - 4, 0);
   const float gx1 = bld1(r.x1, v, 0), gx1m = bld1(r.x1, v - 4, 0);
@@ -352,6 +373,7 @@ __device__ __forceinline__ void vol_block(cx (&a)[N1], const VolRowsU& r, int W)
   const float gzm0 = bld1(r.zm0, v, 0), gzm1 = bld1(r.zm1, v, 0);
   a[Y1] = {((gx0 - gx0m) + (gy0 - gym)) + (gz0 - gzm0),
            ((gx1 - gx1m) + (gy1 - gy0)) + (gz1 - gzm1)};
+  vol_low<N1, Y1>(w, gx0, gy0, gz0, gx1, gy1, gz1);
 }
 // Several slots per wavefront: per-lane offsets into volume-wide descriptors.
 struct VolRowsL {
@@ -362,7 +384,7 @@ struct VolRowsL {
   int lane;
 };
 template <int N1, int N2, int Y1>
-__device__ __forceinline__ void vol_block(cx (&a)[N1], const VolRowsL& r, int W) {
+__device__ __forceinline__ void vol_block(cx (&a)[N1], VolLow& w, const VolRowsL& r, int W) {
   const int lim = W - N2 * Y1;
   const bool xin = r.lane < lim, xmin = r.lane <= lim;
   constexpr int so = N2 * Y1 * 4, som = Y1 == 0 ? 0 : N2 * Y1 * 4 - 4;
@@ -377,13 +399,14 @@ __device__ __forceinline__ void vol_block(cx (&a)[N1], const VolRowsL& r, int W)
   const float gzm0 = bld1(r.gz, q0, so), gzm1 = bld1(r.gz, q1, so);
   a[Y1] = {((gx0 - gx0m) + (gy0 - gym)) + (gz0 - gzm0),
            ((gx1 - gx1m) + (gy1 - gy0)) + (gz1 - gzm1)};
+  vol_low<N1, Y1>(w, gx0, gy0, gz0, gx1, gy1, gz1);
 }
 template <int N1, int N2, int NB, int Y1, class Rows>
-__device__ __forceinline__ void vol_load(cx (&a)[N1], const Rows& r, int W) {
+__device__ __forceinline__ void vol_load(cx (&a)[N1], VolLow& w, const Rows& r, int W) {
   if constexpr (Y1 < N1) {
-    if constexpr (Y1 < NB) vol_block<N1, N2, Y1>(a, r, W);
+    if constexpr (Y1 < NB) vol_block<N1, N2, Y1>(a, w, r, W);
     else a[Y1] = {0.f, 0.f};
-    vol_load<N1, N2, NB, Y1 + 1>(a, r, W);
+    vol_load<N1, N2, NB, Y1 + 1>(a, w, r, W);
   }
 }
 
@@ -433,8 +456,13 @@ __device__ __forceinline__ void low_lane_factors(cx (&ax0)[kLowBins], cx (&ax1)[
 template <int N1, int N2>
 constexpr int kFwdPlane =
     cmax(RowCfg<N1, N2>::LDSC, (4 * (2 * kLowBins + 1) * (RowCfg<N1, N2>::G + 1) + 1) / 2);
-template <int N1, int N2, int SLOTS>
-constexpr int kFwdLds = SLOTS * 2 * kFwdPlane<N1, N2>;  // floats per workgroup
+// volume slices also sum Ez: 3K + 2 complex low-bin values per row
+template <int N1, int N2>
+constexpr int kFwdPlane3 =
+    cmax(RowCfg<N1, N2>::LDSC, (4 * (3 * kLowBins + 2) * (RowCfg<N1, N2>::G + 1) + 1) / 2);
+template <int N1, int N2, int SLOTS, int EDIT = kEditNone>
+constexpr int kFwdLds =  // floats per workgroup
+    SLOTS * 2 * (EDIT == kIn3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>);
 template <int N1, int N2, int SLOTS>
 constexpr int kInvLds = SLOTS * 2 * RowCfg<N1, N2>::LDSC;
 
@@ -443,10 +471,12 @@ template <int N1, int N2, int SLOTS, int NB, int EDIT = kEditNone>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, float* lds) {
   using C = RowCfg<N1, N2>;
   constexpr int KL = kLowBins;
-  constexpr int NC = 2 * KL + 1;         // low-bin complex values per row
+  constexpr bool IS3D = EDIT == kIn3D;
+  // low-bin complex values per row: Ex bins 1..K, Ey bins 0..K (and Ez bins 0..K, volumes)
+  constexpr int NC = 2 * KL + 1 + (IS3D ? KL + 1 : 0);
   constexpr int NV = 4 * NC;             // floats per lane to sum: two rows, re and im
   constexpr int RS = C::G + 1;           // LDS stride of one value over the lanes
-  constexpr int PLANE = kFwdPlane<N1, N2>;
+  constexpr int PLANE = IS3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>;
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
   float* re = lds + slot * 2 * PLANE;
@@ -462,7 +492,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     gyi = p.gy + vplane * p.img_in;
   }
   const rsrc_t rT1 = make_buf(p.T1 + tplane * p.img_t1, p.img_t1 * 8);
-  const rsrc_t rSB = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
+  // side arrays: per image, or per (volume, plane z of zp) like T1
+  const rsrc_t rSB = make_buf(p.SB + tplane * p.img_sb, p.img_sb * 8);
+  const rsrc_t rSZ = make_buf(IS3D ? p.SZ + tplane * p.img_sb : p.SB, IS3D ? p.img_sb * 8 : 0);
   const rsrc_t rtw = make_buf(p.twA, (long long)C::N * 8);
   const rsrc_t rtl = make_buf(p.twL, (long long)2 * (KL + 1) * C::G * 8);
   const rsrc_t rgx = make_buf(gxi, p.img_in * 4);
@@ -474,11 +506,26 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     const bool ok = q < p.npairs;
     const int y0 = 2 * q;
     cx a[N1];
-    cx ax0[KL], ay0[KL + 1], ax1[KL], ay1[KL + 1];
+    cx ax0[KL], ay0[KL + 1], ax1[KL], ay1[KL + 1], az0[KL + 1], az1[KL + 1];
 #pragma unroll
     for (int l = 0; l < KL; ++l) ax0[l] = ax1[l] = {0.f, 0.f};
 #pragma unroll
-    for (int l = 0; l <= KL; ++l) ay0[l] = ay1[l] = {0.f, 0.f};
+    for (int l = 0; l <= KL; ++l) ay0[l] = ay1[l] = az0[l] = az1[l] = {0.f, 0.f};
+    // volumes: copy the loader's sums into the arrays above
+    auto take = [&](const VolLow& w) {
+#pragma unroll
+      for (int l = 0; l < KL; ++l) {
+        ax0[l] = w.ax0[l];
+        ax1[l] = w.ax1[l];
+      }
+#pragma unroll
+      for (int l = 0; l <= KL; ++l) {
+        ay0[l] = w.ay0[l];
+        ay1[l] = w.ay1[l];
+        az0[l] = w.az0[l];
+        az1[l] = w.az1[l];
+      }
+    };
     float cy[2] = {0.f, 0.f};  // x - 1 of the first y1 block: outside the image
     auto row = [&](const float* img, int y) {
       const bool in = ok && y >= 0 && y < p.H;
@@ -499,7 +546,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
                           prow(gyi, pz, y0), prow(gyi, pz, y0 + 1), prow(gzi, pz, y0),
                           prow(gzi, pz, y0 + 1), prow(gzi - p.img_in, pm, y0),
                           prow(gzi - p.img_in, pm, y0 + 1), (lane < N2 ? lane * 4 : kOOB) + tz};
-      vol_load<N1, N2, NB, 0>(a, rows, p.W);
+      VolLow w{};
+      vol_load<N1, N2, NB, 0>(a, w, rows, p.W);
+      take(w);
     } else if constexpr (EDIT == kIn3D) {
       const bool pz = vz < p.zd, pm = vz >= 1;
       const float* gzi = p.gz + vplane * p.img_in;
@@ -515,7 +564,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
                           make_buf(gzi - lo, (lo + p.img_in) * 4), voff(pz, zp1, y0 - 1), z0, z1,
                           voff(pm, 0, y0), voff(pm, 0, y0 + 1),
                           lane > 0 ? z0 - 4 : kOOB, lane > 0 ? z1 - 4 : kOOB, lane};
-      vol_load<N1, N2, NB, 0>(a, rows, p.W + tz);
+      VolLow w{};
+      vol_load<N1, N2, NB, 0>(a, w, rows, p.W + tz);
+      take(w);
     } else if constexpr (EDIT == kInLaplacian && SLOTS == 1) {
       const float* li = p.C + b * (long long)(p.H + 1) * (p.W + 1);
       auto lrow = [&](int y) {
@@ -558,8 +609,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     }
 
     // lane factors w_N^(l j) (Ex also times 1 - w_N^l), then the sums over the lanes
-    // a given Laplacian or a volume slice: every bin comes from the FFT (no split)
-    constexpr bool FULLBINS = EDIT == kInLaplacian || EDIT == kIn3D;
+    // a given Laplacian: every bin comes from the FFT (no split)
+    constexpr bool FULLBINS = EDIT == kInLaplacian;
     constexpr int NVL = FULLBINS ? 0 : (NV + C::G - 1) / C::G;
     float lowsum[NVL > 0 ? NVL : 1];
     if constexpr (!FULLBINS) {
@@ -574,11 +625,22 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
 #pragma unroll
     for (int l = 2; l <= KL; ++l) wp[l] = (l % 2 == 0) ? cmul(wp[l / 2], wp[l / 2]) : cmul(wp[l - 1], wp[1]);
     low_lane_factors<C::N>(ax0, ax1, ay0, ay1, wp, std::make_integer_sequence<int, KL>{});
-    // value index: row r of the pair, complex index c < NC (Ex bins 1..K, then Ey bins 0..K)
+    if constexpr (IS3D) {
+#pragma unroll
+      for (int l = 1; l <= KL; ++l) {
+        az0[l] = cmul(az0[l], wp[l]);
+        az1[l] = cmul(az1[l], wp[l]);
+      }
+    }
+    // value index: row r of the pair, complex index c < NC (Ex bins 1..K, then Ey bins
+    // 0..K, then for volumes Ez bins 0..K)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const cx v0 = c < KL ? ax0[c < KL ? c : 0] : ay0[c < KL ? 0 : c - KL];
-      const cx v1 = c < KL ? ax1[c < KL ? c : 0] : ay1[c < KL ? 0 : c - KL];
+      constexpr int E2 = 2 * KL + 1;
+      const cx v0 = c < KL ? ax0[c < KL ? c : 0]
+                           : c < E2 ? ay0[c < E2 ? c - KL : 0] : az0[c < E2 ? 0 : c - E2];
+      const cx v1 = c < KL ? ax1[c < KL ? c : 0]
+                           : c < E2 ? ay1[c < E2 ? c - KL : 0] : az1[c < E2 ? 0 : c - E2];
       re[(2 * c) * RS + lane] = v0.x;
       re[(2 * c + 1) * RS + lane] = v0.y;
       re[(2 * NC + 2 * c) * RS + lane] = v1.x;
@@ -598,7 +660,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     slot_sync();
     }  // !FULLBINS
 
-    fwd_fft_to_lds<N1, N2, FULLBINS>(a, re, im, lane, rtw, tz);
+    fwd_fft_to_lds<N1, N2, FULLBINS || IS3D>(a, re, im, lane, rtw, tz);
 
     // Z = FFT(L[y0] + i L[y0+1]): L^[y0, l] = (Z[l] + conj Z[N-l]) / 2,
     // L^[y0+1, l] = (Z[l] - conj Z[N-l]) / 2i; bins l <= K come from the direct sums
@@ -641,8 +703,10 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         const int y = y0 + rr;
         if (c < KL) {
           if (y <= p.H) bst1(rT1, lowsum[k], (y * C::NHP + c + 1) * 8 + comp * 4, 0);
+        } else if (c < 2 * KL + 1) {
+          if (y < p.H) bst1(rSB, lowsum[k], (y * p.KP + c - KL) * 8 + comp * 4, 0);
         } else if (y < p.H) {
-          bst1(rSB, lowsum[k], (y * p.KP + c - KL) * 8 + comp * 4, 0);
+          bst1(rSZ, lowsum[k], (y * p.KP + c - 2 * KL - 1) * 8 + comp * 4, 0);
         }
       }
     }
@@ -664,7 +728,7 @@ template <int N1, int N2, int SLOTS, int NB, int EDIT>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 __attribute__((amdgpu_waves_per_eu(kFwdWaves<N1, SLOTS, NB, EDIT>)))
 k_row_fwd(RowFwdArgs p) {
-  __shared__ float lds[kFwdLds<N1, N2, SLOTS>];
+  __shared__ float lds[kFwdLds<N1, N2, SLOTS, EDIT>];
   int bx, by;
   xcd_contiguous(bx, by);
   row_fwd_body<N1, N2, SLOTS, NB, EDIT>(p, bx, by, lds);

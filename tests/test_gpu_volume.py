@@ -50,16 +50,23 @@ def _fields(seed, B, D, H, W):
 SHAPES = [  # D, H, W, P, M, N: default tori, an odd size, minimal padding, a deeper volume
     (8, 16, 16, 0, 0, 0), (13, 21, 30, 0, 0, 0), (10, 12, 14, 12, 14, 16),
     (33, 40, 48, 0, 0, 0), (64, 64, 64, 0, 0, 0),
-    (4, 10, 256, 0, 0, 0),     # long rows: the 512 limit of the x extent
+    (4, 10, 256, 0, 0, 0),     # long rows
+    (4, 10, 600, 0, 0, 0),     # rows of 1200: the literal transform of the divergence
+                               # gave 1.4e-5 here; the split bins keep it near 1e-6
+    (4, 40, 1200, 0, 0, 0),    # the longest row FFT (2400)
+    (8, 600, 8, 0, 0, 0),      # long columns (M = 1200)
     (200, 12, 10, 0, 0, 0),    # a deep volume: z transform of length 400
 ]
 
 
-def test_volume_extents_beyond_512_are_refused():
+def test_volume_plan_limits():
+    """The z transform is compiled for depths P <= 512 and the rows for the supported row
+    lengths (up to 2400); other sizes are refused."""
     with pytest.raises(gfc.GFCError):
-        gfc.Plan3(4, 10, 600)  # default N = 1200
+        gfc.Plan3(300, 8, 8)     # default P = 600
     with pytest.raises(gfc.GFCError):
-        gfc.Plan3(300, 8, 8)   # default P = 600
+        gfc.Plan3(4, 8, 1300)    # default N = 2600 has no row FFT
+    gfc.Plan3(4, 8, 1200)        # N = 2400 is accepted
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])) + f"@{s[3] or 'd'}")
