@@ -57,11 +57,6 @@ ColGeom col_geometry(int R, int M, int r0, int rows, int C_req) {
 
 }  // namespace
 
-
-namespace {
-
-}  // namespace
-
 // Per column (kz, l) of a P x M x N problem (P = 1 for images): the recursion constants for
 // beta = 4 sin^2(pi l / N) + 4 sin^2(pi kz / P), the output scale 1 / (N P) (the row and z
 // inverse transforms are unnormalised), and the reference weights for the corner at

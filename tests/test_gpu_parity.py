@@ -169,6 +169,22 @@ def test_forward_batch801x1200_sampled():
         assert e <= TOL
 
 
+def test_backward_batch801x1200_sampled():
+    """The backward solve of 100 images of 801x1200 in one call, as the benchmark's fwd+bwd
+    step launches it (the column pass then runs its low tiles on the side stream); the
+    oracle checks sampled images."""
+    _say("backward parity 801x1200 B=100 (sampled)")
+    H, W, M, N, B = 801, 1200, 1620, 2400, 100
+    du = (np.random.default_rng(8011200).normal(size=(B, H, W)) * 0.1 + 0.01).astype(np.float32)
+    dgx, dgy = _gpu_backward(du, M, N)
+    assert np.all(np.isfinite(dgx)) and np.all(np.isfinite(dgy))
+    for i in (0, 57, 99):
+        rx, ry = O.solve_backward(du[i:i + 1], M, N)
+        e = rel_l2(np.concatenate([dgx[i], dgy[i]]), np.concatenate([rx[0], ry[0]]))
+        _say(f"  image {i}: rel L2 {e:.3e}")
+        assert e <= TOL
+
+
 def test_forward_merge512_sampled():
     _say("forward parity merge512 (sampled)")
     w = synth.make_workload("merge512")
