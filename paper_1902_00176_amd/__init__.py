@@ -47,7 +47,8 @@ def lib():
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB_PATH):
-                raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+                raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                                   "python paper_1902_00176_amd/build_lib.py")
             L = ctypes.CDLL(_LIB_PATH)
             vp, i, u, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
             ip = ctypes.POINTER(ctypes.c_int)
