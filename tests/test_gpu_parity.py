@@ -81,6 +81,8 @@ SHAPES = [
     (129, 200, 260, 400),
     (255, 300, 513, 640),
     (3, 1250, 8, 2400),    # 2W > N on the longest rows: every element column is loaded
+    (2, 2398, 6, 2400),    # the widest image a plan accepts (W = N - 2) on the longest rows
+    (3, 2046, 6, 2048),    # the same on the longest power-of-two row
     (2, 1200, 6, 2400),    # the widest default row (one FFT slot per wavefront), K = 32
     (8, 1200, 16, 2400),   # thin and wide: 16 row bins split
     (16, 1200, 32, 2400),  # 8 row bins split
@@ -242,7 +244,8 @@ def test_nonfinite_input_propagates():
 
 @pytest.mark.parametrize("H,W,M,N", [(64, 64, 128, 128), (31, 45, 64, 96), (100, 37, 210, 80),
                                      (1, 37, 3, 80), (33, 70, 35, 72), (129, 200, 260, 400),
-                                     (2, 1200, 6, 2400), (5000, 6, 10000, 16)])
+                                     (2, 1200, 6, 2400), (2, 2398, 6, 2400),
+                                     (5000, 6, 10000, 16)])
 def test_backward_parity(H, W, M, N):
     _say(f"backward parity H={H} W={W} M={M} N={N}")
     rng = np.random.default_rng(H + 3 * W)
