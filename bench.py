@@ -6,7 +6,7 @@ line: solves/s, per-kernel times from HIP events recorded between the passes on 
 stream, the roofline of the dominant kernel, forward+backward pairs/s, and the float64 CPU
 oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--no-bwd]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 30] [--no-cpu] [--no-bwd]
 """
 from __future__ import annotations
 
@@ -258,7 +258,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-color", action="store_true")
@@ -332,11 +332,22 @@ def main():
             stage_fwd(k)
     torch.cuda.synchronize()
 
+    # The K timed steps run back to back with nothing between the passes; the stage times
+    # come from K more steps with an event after each pass.
     names = ["k_row_fwd", "k_col_fwd", "k_row_inv"]
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        for k in (1, 2, 3):
+            stage_fwd(k)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     t_start.record(stream)
     for i in range(args.steps):
         ev[i][0].record(stream)
@@ -345,8 +356,7 @@ def main():
             ev[i][k].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
-    ms_total = t_start.elapsed_time(t_end)
-    ms_step = ms_total / args.steps
+    ms_step_ev = t_start.elapsed_time(t_end) / args.steps
     stage_ms = {n: sum(ev[i][k].elapsed_time(ev[i][k + 1]) for i in range(args.steps)) / args.steps
                 for k, n in enumerate(names)}
 
@@ -378,6 +388,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "H": H, "W": W_, "M": w.M, "N": w.N, "batch": B},
         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "ms_per_step_with_stage_events": ms_step_ev,
         "path_hbm_frac": total_bytes / (ms_step / 1e3) / HBM_PEAK,
         "roofline": roof,
     }
@@ -471,13 +482,19 @@ def main():
         for i in range(nb):
             for k in (1, 2, 3):
                 stage_fwd(k)
+            for k in (1, 2, 3):
+                stage_bwd(k)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_pair = t0.elapsed_time(t1) / nb
+        for i in range(nb):  # stage times, as for the forward steps
+            for k in (1, 2, 3):
+                stage_fwd(k)
             evb[i][0].record(stream)
             for k in (1, 2, 3):
                 stage_bwd(k)
                 evb[i][k].record(stream)
-        t1.record(stream)
         torch.cuda.synchronize()
-        ms_pair = t0.elapsed_time(t1) / nb
         bms = {n: sum(evb[i][k].elapsed_time(evb[i][k + 1]) for i in range(nb)) / nb
                for k, n in enumerate(names_b)}
         mb = stage_model(H, W_, w.N, K, Kb, "bwd")
