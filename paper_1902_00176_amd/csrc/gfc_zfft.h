@@ -11,6 +11,10 @@
 
 namespace gfc {
 
+// A byte offset past every volume's spectra, which plans keep below 2^31 bytes: loads at it
+// return zero.
+constexpr int kZOob = 0x7ffffff8;
+
 template <int P1, int P2>
 struct ZCfg {
   static constexpr int P = P1 * P2;
@@ -42,7 +46,8 @@ k_zfft(ZfftArgs a) {
     const int c = i % TL, z = i / TL;
     const int l = l0 + c;
     const bool in = z < a.din && l < a.NH;
-    const f2b v = bld2(rT, in ? int(((long long)z * a.plane + (long long)y * a.NHP + l) * 8) : 0x70000000, 0);
+    const long long e = (long long)z * a.plane + (long long)y * a.NHP + l;
+    const f2b v = bld2(rT, in ? int(e * 8) : kZOob, 0);
     s_lds[c][z] = v.x;
     s_lds[c][C::S + z] = v.y;
   }

@@ -99,3 +99,31 @@ def test_framed_volume_reconstructs():
     dev = torch.device("cuda:0")
     u = gfc.solve3(*(torch.from_numpy(a).to(dev) for a in g)).cpu().numpy()[0]
     assert np.linalg.norm(u - S) / np.linalg.norm(S) <= TOL
+
+
+def test_volume_spectra_near_two_gib():
+    """A volume whose spectra take 2.0e9 bytes (P x (H+1) x row stride x 8 just under 2^31):
+    the z transform's zero planes must still read as zero there. The workspace first holds
+    another solve's spectra, so stale values would show; a framed conservative volume is the
+    check (the oracle's float64 transform of 5e8 points is not run)."""
+    D, H, W, P, M, N = 8, 479, 1000, 512, 486, 2000
+    _say(f"volume D={D} H={H} W={W} on {P}x{M}x{N}")
+    plan = gfc.Plan3(D, H, W, P, M, N).build()
+    dev = torch.device("cuda:0")
+    ws = torch.empty(plan.workspace_size(1), dtype=torch.uint8, device=dev)
+    assert ws.numel() >= 2_000_000_000
+    rng = np.random.default_rng(2000)
+    noise = [torch.from_numpy(rng.normal(size=(1, D, H, W)).astype(np.float32)).to(dev)
+             for _ in range(3)]
+    plan.solve(*noise, workspace=ws)
+    S = _gauss_volume(rng, D, H, W)
+    S[0], S[:, 0], S[:, :, 0] = 0.0, 0.0, 0.0
+    g = []
+    for ax in (2, 1, 0):
+        Sp = np.concatenate([S, np.zeros_like(np.take(S, [0], axis=ax))], axis=ax)
+        g.append(torch.from_numpy(np.diff(Sp, axis=ax).astype(np.float32)[None]).to(dev))
+    u = plan.solve(*g, workspace=ws).cpu().numpy()[0]
+    e = np.linalg.norm(u - S) / np.linalg.norm(S)
+    _say(f"  rel L2 {e:.3e}")
+    assert e <= TOL
+
