@@ -267,8 +267,10 @@ const char* gfc_status_str(gfc_status s);
  * spectrum is 1/lambda with lambda = -4 sin^2(pi kz/P) - 4 sin^2(pi ky/M) - 4 sin^2(pi kx/N),
  * the 7-point stencil's symbol, and 0 at the DC bin). A D x H x W volume sits centred in a
  * P x M x N torus (P = 0: the smallest even 2/3/5-smooth P >= 2D, likewise M, N);
- * u = v[block] - v[0,0,0]. P is at most 512 and N a supported row length (GFC_E_SIZE
- * otherwise); M and N follow gfc_plan_create's rules.
+ * u = v[block] - v[0,0,0]. P is at most 512 and N a supported row length; M and N follow
+ * gfc_plan_create's rules; one volume's spectra, P x (H+1) x (N/2+1, rounded up to a
+ * multiple of 32) complex float32, stay below 2^31 bytes and one volume below 2^30 bytes
+ * (GFC_E_SIZE otherwise).
  *   gx, gy, gz : [B][D][H][W] float32 forward-difference fields, zero exterior
  *   u          : [B][D][H][W] float32
  * Passes: rows of the 7-point divergence (x), whose 5 lowest row frequencies are kept as
