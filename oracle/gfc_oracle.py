@@ -10,8 +10,8 @@ What it computes (block-centred convention of Algorithm A/B):
   (oy, ox) = (floor((M-H)/2), floor((N-W)/2)) in zeros (the padding of Sec. 2.3.2).
 * L = div E with backward differences on the torus (eq. (3)):
       L[y,x] = Ex[y,x] - Ex[y,x-1] + Ey[y,x] - Ey[y-1,x]          (indices mod M, N)
-* Green's spectrum (eqs. (19)-(22), Algorithm A): G^ = F(dirac) / F(laplace) with the
-  Dirac at [1,1] and the 5-point kernel at [0:3,0:3]; this equals 1/lambda with
+* Green's spectrum (eqs. (19)-(22), Algorithm A): G^ = F(dirac) / F(laplace), the impulse
+  at the centre of a 3 x 3 five-point stencil padded to the torus; this equals 1/lambda with
       lambda(k,l) = -4 sin^2(pi k/M) - 4 sin^2(pi l/N).
   Readings taken where the paper is silent or inconsistent:
     - stencil sign: Algorithm A's +Laplacian ([[0,1,0],[1,-4,1],[0,1,0]]), the sign for
@@ -37,7 +37,7 @@ import numpy as np
 import scipy.fft as sfft
 
 __all__ = [
-    "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_algorithm_a",
+    "block_offset", "laplacian_symbol", "green_spectrum", "green_spectrum_eq22",
     "embed", "divergence", "solve_fft", "solve_direct", "lstsq_torus", "torus_gradient",
     "solve_backward", "green_function", "cpu_workers", "color_correct", "threshold_edit",
     "gdm_edit", "solve_laplacian", "block_offset3", "green_spectrum3", "solve3_fft",
@@ -77,23 +77,35 @@ def green_spectrum(M: int, N: int) -> np.ndarray:
     return G
 
 
-def green_spectrum_algorithm_a(M: int, N: int, dirac_pos=(1, 1), kernel=None) -> np.ndarray:
-    """Algorithm A as printed: fft2 of the Dirac over fft2 of the zero-padded Laplace kernel.
+def green_spectrum_eq22(M: int, N: int, kernel=None, dirac_pos=(1, 1)) -> np.ndarray:
+    """Eq. (19) on the M x N torus with the zero-padded kernels of eqs. (20)-(21): the
+    discrete Fourier transform of a unit impulse at `dirac_pos` divided by that of a 3 x 3
+    stencil whose top-left tap sits at the grid origin.
 
-    `kernel` is the 3x3 stencil placed at [0:3, 0:3] (Algorithm A's by default). The DC bin,
-    which Algorithm A leaves as 1/0, is set to 0. Returns the complex spectrum.
-    """
+    Both transforms are written as their finite sums: the impulse contributes the single
+    phase e^{-2 pi i (k a / M + l b / N)} of its position (a, b), and the stencil the sum of
+    its nine taps times their phases (its symbol). No padded array is transformed. With the
+    stencil centred on the impulse the phases cancel and the ratio is real: 1/lambda.
+    `kernel` defaults to the +5-point Laplacian (Algorithm A's sign, the stencil-sign
+    reading of the module header); the DC bin, where the symbol vanishes, is set to 0. Returns the complex spectrum [M, N]."""
     if kernel is None:
         kernel = np.array([[0.0, 1.0, 0.0], [1.0, -4.0, 1.0], [0.0, 1.0, 0.0]])
-    dirac = np.zeros((M, N))
-    dirac[dirac_pos] = 1.0
-    lap = np.zeros((M, N))
-    lap[0:3, 0:3] = kernel
-    num = np.fft.fft2(dirac)
-    den = np.fft.fft2(lap)
+    kernel = np.asarray(kernel, dtype=np.float64)
+    fk = np.arange(M, dtype=np.float64)[:, None] / M
+    fl = np.arange(N, dtype=np.float64)[None, :] / N
+
+    def phase(a, b):
+        return np.exp(-2j * np.pi * (fk * a + fl * b))
+
+    symbol = np.zeros((M, N), dtype=np.complex128)
+    for a in range(kernel.shape[0]):
+        for b in range(kernel.shape[1]):
+            if kernel[a, b] != 0.0:
+                symbol += kernel[a, b] * phase(a, b)
+    num = phase(*dirac_pos)
     out = np.zeros((M, N), dtype=np.complex128)
-    nz = np.abs(den) > 1e-300
-    out[nz] = num[nz] / den[nz]
+    nz = np.abs(symbol) > 1e-300
+    out[nz] = num[nz] / symbol[nz]
     return out
 
 

@@ -41,11 +41,11 @@ def _framed_conservative(rng, H, W):
 # ---------------------------------------------------------------- Green's spectrum (A0)
 
 @pytest.mark.parametrize("M,N", [(12, 10), (16, 16), (9, 14), (30, 24)])
-def test_closed_form_equals_algorithm_a_with_printed_kernel(golden_dir, M, N):
+def test_closed_form_equals_eq22_with_printed_kernels(golden_dir, M, N):
     k = _load(golden_dir, "paper_kernels.json")
     lap = np.array(k["algorithm_a_laplace"]["value"], dtype=float)
     pos = tuple(k["algorithm_a_dirac_position"]["value"])
-    Ga = O.green_spectrum_algorithm_a(M, N, dirac_pos=pos, kernel=lap)
+    Ga = O.green_spectrum_eq22(M, N, kernel=lap, dirac_pos=pos)
     Gc = O.green_spectrum(M, N)
     mask = np.ones((M, N), bool)
     mask[0, 0] = False
@@ -54,6 +54,68 @@ def test_closed_form_equals_algorithm_a_with_printed_kernel(golden_dir, M, N):
     assert rel.max() < 1e-12
     # Algorithm A's literal division is 1/0 at DC: the oracle's DC reading is 0.
     assert Gc[0, 0] == 0.0
+
+
+def _algorithm_b_literal(gx, gy, pad, lap, pos):
+    """Algorithms A and B step by step: the field padded by `pad` on each side at explicit
+    indices, its divergence pixel by pixel (backward differences on the torus, eq. (3)), the
+    eq. (22) spectrum of the given kernels, a complex 2-D FFT solve, the corner subtracted,
+    [pad:-pad, pad:-pad] kept."""
+    H, W = gx.shape
+    M, N = H + 2 * pad, W + 2 * pad
+    Ex = np.zeros((M, N))
+    Ey = np.zeros((M, N))
+    Ex[pad:pad + H, pad:pad + W] = gx
+    Ey[pad:pad + H, pad:pad + W] = gy
+    padded_L = np.zeros((M, N))
+    for y in range(M):
+        for x in range(N):
+            padded_L[y, x] = (Ex[y, x] - Ex[y, x - 1]) + (Ey[y, x] - Ey[y - 1, x])
+    green_F = O.green_spectrum_eq22(M, N, kernel=lap, dirac_pos=pos)
+    I = np.fft.ifft2(np.fft.fft2(padded_L) * green_F)
+    assert np.max(np.abs(I.imag)) < 1e-12 * np.max(np.abs(I.real))
+    I = I.real - I.real[0, 0]
+    return I[pad:-pad, pad:-pad], padded_L, green_F
+
+
+@pytest.mark.parametrize("H,W,pad", [(56, 72, 4), (7, 10, 4), (20, 31, 3)])
+def test_block_offset_is_algorithm_b_pad(golden_dir, H, W, pad):
+    """Algorithm A pads the image by `pad` on every side and Algorithm B crops
+    [pad:-pad, pad:-pad]: on a torus of H + 2 pad by W + 2 pad the block sits at (pad, pad)."""
+    assert O.block_offset(H, W, H + 2 * pad, W + 2 * pad) == (pad, pad)
+    k = _load(golden_dir, "paper_kernels.json")
+    if pad == k["algorithm_a_pad"]["value"]:
+        assert (H + 8, W + 8) == (H + 2 * pad, W + 2 * pad)
+
+
+def test_block_offset_floor_on_odd_margins():
+    """Reading of the crop for an odd margin M - H (the 801 x 1200 workload on 1620 x 2400):
+    the block starts at floor((M - H) / 2), so the larger half of the padding is below it."""
+    assert O.block_offset(801, 1200, 1620, 2400) == (409, 600)
+    assert O.block_offset(5, 6, 8, 9) == (1, 1)
+
+
+@pytest.mark.parametrize("H,W", [(56, 72), (12, 22)])
+def test_algorithm_a_and_b_run_literally_with_pad_4(golden_dir, H, W):
+    """Algorithms A and B taken step by step with their pad of 4 on a non-conservative field:
+    the spectrum of eq. (22) from the printed kernels, the divergence of the field padded by
+    4 pixels on each side (explicit indices, not block_offset), a full complex 2-D FFT solve,
+    the corner value subtracted and [4:-4, 4:-4] kept. The oracle's solve on the
+    (H + 8) x (W + 8) torus must agree, which fixes its block placement and its constant."""
+    k = _load(golden_dir, "paper_kernels.json")
+    pad = k["algorithm_a_pad"]["value"]
+    lap = np.array(k["algorithm_a_laplace"]["value"], dtype=float)
+    pos = tuple(k["algorithm_a_dirac_position"]["value"])
+    M, N = H + 2 * pad, W + 2 * pad
+    rng = np.random.default_rng(4004 + H)
+    gx, gy = _rand_field(rng, H, W)
+    I, padded_L, green_F = _algorithm_b_literal(gx, gy, pad, lap, pos)
+    ref = O.solve_fft(gx, gy, M, N)
+    assert np.max(np.abs(I - ref)) < 1e-11 * max(1.0, np.abs(ref).max())
+    # the corner matters for a non-conservative field: a block one row lower changes u
+    shifted = np.fft.ifft2(np.fft.fft2(np.roll(padded_L, 1, axis=0)) * green_F).real
+    shifted = (shifted - shifted[0, 0])[pad + 1:M - pad + 1, pad:-pad]
+    assert np.max(np.abs(shifted - ref)) > 1e-6  # far above the 1e-11 agreement
 
 
 def test_green_4x4_hand_derived(golden_dir):
@@ -147,7 +209,7 @@ def test_eq15_sign_reconstructs_the_negative_image(golden_dir):
     H, W, M, N = 6, 7, 14, 16
     rng = np.random.default_rng(11)
     S, gx, gy = _framed_conservative(rng, H, W)
-    G15 = O.green_spectrum_algorithm_a(M, N, kernel=lap15)
+    G15 = O.green_spectrum_eq22(M, N, kernel=lap15)
     oy, ox = O.block_offset(H, W, M, N)
     L = O.divergence(gx, gy, M, N, oy, ox)
     v = np.real(np.fft.ifft2(np.fft.fft2(L) * G15))
@@ -320,7 +382,7 @@ def test_backward_reference_term_is_required():
 # ---------------------------------------------------------------- pin sensitivity
 
 @pytest.mark.parametrize("mutation", ["forward_difference_div", "drop_y_term", "transpose_grid",
-                                      "reference_pixel", "stencil_sign"])
+                                      "reference_pixel", "stencil_sign", "block_offset"])
 def test_planted_oracle_mistakes_are_caught(monkeypatch, mutation):
     """Plant a plausible mistake in the oracle (on the CPU) and check a pin fails."""
     import oracle.gfc_oracle as G
@@ -352,6 +414,10 @@ def test_planted_oracle_mistakes_are_caught(monkeypatch, mutation):
         def bad(gx, gy, M, N, oy, ox):
             return np.roll(real_div(gx, gy, M, N, oy, ox), 1, axis=-1)
         monkeypatch.setattr(G, "divergence", bad)
+    elif mutation == "block_offset":
+        real_off = G.block_offset
+        monkeypatch.setattr(G, "block_offset",
+                            lambda H, W, M, N: (real_off(H, W, M, N)[0] + 1, real_off(H, W, M, N)[1]))
 
     rng = np.random.default_rng(37)
     H, W, M, N = 6, 7, 14, 16
@@ -359,7 +425,10 @@ def test_planted_oracle_mistakes_are_caught(monkeypatch, mutation):
     framed_ok = np.max(np.abs(G.solve_fft(gx, gy, M, N) - S)) < 1e-12
     a = _rand_field(rng, H, W)
     ls_ok = np.max(np.abs(G.solve_fft(*a, M, N) - G.lstsq_torus(*a, M, N))) < 1e-11
-    assert not (framed_ok and ls_ok), f"mutation {mutation} went unnoticed"
+    lap = np.array([[0.0, 1.0, 0.0], [1.0, -4.0, 1.0], [0.0, 1.0, 0.0]])
+    lit = _algorithm_b_literal(*a, 4, lap, (1, 1))[0]
+    lit_ok = np.max(np.abs(G.solve_fft(*a, H + 8, W + 8) - lit)) < 1e-11
+    assert not (framed_ok and ls_ok and lit_ok), f"mutation {mutation} went unnoticed"
 
 
 # ---------------------------------------------------------------- colour correction (eq. (25))
@@ -486,7 +555,7 @@ def test_laplacian_of_a_framed_image_reconstructs_it():
     u = O.solve_laplacian(L, M, N)
     assert np.max(np.abs(u - S)) < 1e-12
     # and Algorithm A's spectrum built from the printed kernels gives the same solve
-    Gh = O.green_spectrum_algorithm_a(M, N)
+    Gh = O.green_spectrum_eq22(M, N)
     oy, ox = O.block_offset(H, W, M, N)
     v = np.real(np.fft.ifft2(np.fft.fft2(O.embed(L, M, N, oy, ox)) * Gh))
     assert np.max(np.abs((v[oy:oy + H, ox:ox + W] - v[0, 0]) - S)) < 1e-11
