@@ -133,9 +133,11 @@ gfc_status gfc_solve_batch_color(gfc_plan_t p, const float* gx, const float* gy,
  *       of an image whose first row and column are zero has exactly this support)
  *   u : [B][H][W] as for gfc_solve_batch.
  * L should sum to 0 (every divergence does): the torus solve cannot represent a net source,
- * and the DC column of L is integrated along y from row 0. Precision: the split of the
- * lowest row frequencies into x- and y-parts that protects gfc_solve_batch is not available
- * for a given L; its row transform is a plain float32 FFT of L.
+ * and the DC column of L is integrated along y from row 0. Precision: the row bins l <= K
+ * (the plan's "low_bins"), which the Green's function amplifies most, are not taken from the
+ * float32 FFT of L: they are direct sums with float64 twiddles and accumulation, handed to
+ * the column pass as running sums over the rows (a float64 scan), so that the sum over the
+ * rows of each such bin is one rounded value rather than a difference of rounded values.
  */
 gfc_status gfc_solve_laplacian(gfc_plan_t p, const float* L, float* u, int B, void* workspace,
                                size_t ws_bytes, void* stream);
@@ -204,7 +206,7 @@ void gfc_plan_destroy(gfc_plan_t p);
  * [off[i], off[i+1]) of gx, gy and u, row-major [H_i][W_i], off[0] = 0,
  * off[i+1] = off[i] + H_i * W_i (gfc_ragged_offsets). A ragged object owns one plan per
  * distinct image size (float64 tables built once) and a schedule of work items; its
- * solve replays a HIP graph captured on the first call with given buffer addresses.
+ * solve replays a HIP graph captured on its first call.
  */
 
 /* gfc_ragged_solve enqueues the passes directly instead of capturing and replaying a graph */
@@ -237,11 +239,14 @@ gfc_status gfc_ragged_workspace_size(gfc_ragged_t r, size_t* bytes);
 
 /*
  * Forward solve of all B images (eqs. (3), (22), (23) and Algorithm B per image): gx, gy,
- * u are packed DEVICE arrays (see above); u must not alias gx or gy. The first call with a
- * given (gx, gy, u, workspace) captures the launch sequence into a HIP graph; later calls
- * with the same addresses only launch the graph on `stream`. A call with other addresses
- * synchronises `stream` once, then captures anew. With GFC_RAGGED_NO_GRAPH every call
- * enqueues the launches itself. Calls that may overlap need separate ragged objects.
+ * u are packed DEVICE arrays (see above); u must not alias gx or gy. The first call
+ * captures the launch sequence into a HIP graph (host-side work); every call then writes
+ * its buffer addresses into a device slot of the ragged object (a one-thread kernel on
+ * `stream`) and launches the graph on `stream`, whose kernels read the addresses from that
+ * slot. Any buffers may be passed on any call; the call never synchronises. With
+ * GFC_RAGGED_NO_GRAPH every call enqueues the launches itself. Calls that may overlap
+ * (other streams or threads) need separate ragged objects. Destroying the object waits for
+ * the last launch of its graph.
  */
 gfc_status gfc_ragged_solve(gfc_ragged_t r, const float* gx, const float* gy, float* u,
                             void* workspace, size_t ws_bytes, void* stream);

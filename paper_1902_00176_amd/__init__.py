@@ -143,6 +143,56 @@ def _stream_ptr(torch, device, stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _nbytes(t) -> int:
+    return t.numel() * t.element_size()
+
+
+def _overlaps(a, b) -> bool:
+    """True when the memory of tensors a and b intersects."""
+    if a is None or b is None or a.numel() == 0 or b.numel() == 0 or a.device != b.device:
+        return False
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    return a0 < b0 + _nbytes(b) and b0 < a0 + _nbytes(a)
+
+
+def check_out(out, shape, dev, inputs=(), name="out"):
+    """Validate a caller-supplied output tensor before its pointer reaches a kernel: float32,
+    contiguous, the expected shape, on `dev`, sharing no memory with the inputs."""
+    import torch
+    if not isinstance(out, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if out.device != dev:
+        raise ValueError(f"{name} is on {out.device}, expected {dev}")
+    if out.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {out.dtype}")
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(shape)}")
+    if not out.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    for t in inputs:
+        if _overlaps(out, t):
+            raise ValueError(f"{name} must not share memory with an input")
+    return out
+
+
+def check_workspace(ws, need: int, dev, others=()):
+    """Validate a caller-supplied workspace: a contiguous tensor on `dev` of at least `need`
+    bytes (any dtype), sharing no memory with the inputs and outputs of the call."""
+    import torch
+    if not isinstance(ws, torch.Tensor):
+        raise TypeError("workspace must be a tensor")
+    if ws.device != dev:
+        raise ValueError(f"workspace is on {ws.device}, expected {dev}")
+    if not ws.is_contiguous():
+        raise ValueError("workspace must be contiguous")
+    if _nbytes(ws) < need:
+        raise ValueError(f"workspace too small: need {need} bytes, got {_nbytes(ws)}")
+    for t in others:
+        if _overlaps(ws, t):
+            raise ValueError("workspace must not share memory with the inputs or outputs")
+    return ws
+
+
 PARAMS = ("row_fppw", "row_ppw", "col_c", "col_rows", "col_rows_b", "low_bins")
 _TUNING_PATH = os.path.join(_HERE, "tuning.json")
 _tuning_db = None
@@ -256,12 +306,12 @@ class Plan:
         gx = gx.contiguous()
         gy = gy.contiguous()
         B = gx.numel() // (self.H * self.W)
-        u = out if out is not None else torch.empty_like(gx)
-        ws = self._workspace(torch, dev, B, workspace)
+        u = check_out(out, gx.shape, dev, (gx, gy)) if out is not None else torch.empty_like(gx)
+        ws = self._workspace(torch, dev, B, workspace, (gx, gy, u))
         with torch.cuda.device(dev):
             _check(lib().gfc_solve_batch(self._h, gx.data_ptr(), gy.data_ptr(), u.data_ptr(), B,
                                          ws.data_ptr() if ws is not None else None,
-                                         ws.numel() if ws is not None else 0,
+                                         _nbytes(ws) if ws is not None else 0,
                                          _stream_ptr(torch, dev, stream)), "gfc_solve_batch")
         return u
 
@@ -279,13 +329,14 @@ class Plan:
         I_std = torch.as_tensor(I_std, dtype=torch.float32, device=dev).reshape(-1).contiguous()
         if I_mean.numel() != B or I_std.numel() != B:
             raise ValueError(f"expected {B} means and standard deviations")
-        u = out if out is not None else torch.empty_like(gx)
-        ws = self._workspace(torch, dev, B, workspace)
+        u = (check_out(out, gx.shape, dev, (gx, gy, I_mean, I_std)) if out is not None
+             else torch.empty_like(gx))
+        ws = self._workspace(torch, dev, B, workspace, (gx, gy, I_mean, I_std, u))
         with torch.cuda.device(dev):
             _check(lib().gfc_solve_batch_color(
                 self._h, gx.data_ptr(), gy.data_ptr(), I_mean.data_ptr(), I_std.data_ptr(),
                 u.data_ptr(), B, ws.data_ptr() if ws is not None else None,
-                ws.numel() if ws is not None else 0, _stream_ptr(torch, dev, stream)),
+                _nbytes(ws) if ws is not None else 0, _stream_ptr(torch, dev, stream)),
                 "gfc_solve_batch_color")
         return u
 
@@ -311,14 +362,15 @@ class Plan:
                 if t.numel() != B:
                     raise ValueError(f"expected {B} means and standard deviations")
             stats.append(t)
-        u = out if out is not None else torch.empty_like(gx)
-        ws = self._workspace(torch, dev, B, workspace)
+        ins = [t for t in (gx, gy, C, *stats) if t is not None]
+        u = check_out(out, gx.shape, dev, ins) if out is not None else torch.empty_like(gx)
+        ws = self._workspace(torch, dev, B, workspace, ins + [u])
         ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
         with torch.cuda.device(dev):
             _check(lib().gfc_solve_edit(
                 self._h, gx.data_ptr(), gy.data_ptr(), ptr(C), modes[mode], float(param),
                 ptr(stats[0]), ptr(stats[1]), u.data_ptr(), B, ptr(ws),
-                ws.numel() if ws is not None else 0, _stream_ptr(torch, dev, stream)),
+                _nbytes(ws) if ws is not None else 0, _stream_ptr(torch, dev, stream)),
                 "gfc_solve_edit")
         return u
 
@@ -334,13 +386,14 @@ class Plan:
         self.build(dev)
         L = L.contiguous()
         B = L.numel() // ((self.H + 1) * (self.W + 1))
-        u = out if out is not None else torch.empty(L.shape[:-2] + (self.H, self.W),
-                                                    dtype=torch.float32, device=dev)
-        ws = self._workspace(torch, dev, B, workspace)
+        shape = L.shape[:-2] + (self.H, self.W)
+        u = (check_out(out, shape, dev, (L,)) if out is not None
+             else torch.empty(shape, dtype=torch.float32, device=dev))
+        ws = self._workspace(torch, dev, B, workspace, (L, u))
         with torch.cuda.device(dev):
             _check(lib().gfc_solve_laplacian(self._h, L.data_ptr(), u.data_ptr(), B,
                                              ws.data_ptr() if ws is not None else None,
-                                             ws.numel() if ws is not None else 0,
+                                             _nbytes(ws) if ws is not None else 0,
                                              _stream_ptr(torch, dev, stream)),
                    "gfc_solve_laplacian")
         return u
@@ -351,22 +404,20 @@ class Plan:
         B = du.numel() // (self.H * self.W)
         dgx = torch.empty_like(du)
         dgy = torch.empty_like(du)
-        ws = self._workspace(torch, dev, B, workspace)
+        ws = self._workspace(torch, dev, B, workspace, (du, dgx, dgy))
         with torch.cuda.device(dev):
             _check(lib().gfc_solve_backward(self._h, du.data_ptr(), dgx.data_ptr(), dgy.data_ptr(), B,
                                             ws.data_ptr() if ws is not None else None,
-                                            ws.numel() if ws is not None else 0,
+                                            _nbytes(ws) if ws is not None else 0,
                                             _stream_ptr(torch, dev, stream)), "gfc_solve_backward")
         return dgx, dgy
 
-    def _workspace(self, torch, dev, B, workspace):
+    def _workspace(self, torch, dev, B, workspace, others=()):
         if B == 0:
             return None
         need = self.workspace_size(B)
         if workspace is not None:
-            if workspace.numel() * workspace.element_size() < need:
-                raise ValueError(f"workspace too small: need {need} bytes")
-            return workspace
+            return check_workspace(workspace, need, dev, others)
         return torch.empty(need, dtype=torch.uint8, device=dev)
 
 
@@ -455,9 +506,10 @@ class Plan3:
         self.build(dev)
         gx, gy, gz = gx.contiguous(), gy.contiguous(), gz.contiguous()
         B = gx.numel() // (self.D * self.H * self.W)
-        u = out if out is not None else torch.empty_like(gx)
+        u = check_out(out, gx.shape, dev, (gx, gy, gz)) if out is not None else torch.empty_like(gx)
         need = self.workspace_size(B)
-        ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=dev)
+        ws = (check_workspace(workspace, need, dev, (gx, gy, gz, u)) if workspace is not None
+              else torch.empty(need, dtype=torch.uint8, device=dev))
         with torch.cuda.device(dev):
             _check(lib().gfc_solve3_batch(self._h, gx.data_ptr(), gy.data_ptr(), gz.data_ptr(),
                                           u.data_ptr(), B, ws.data_ptr(),
@@ -560,15 +612,17 @@ class Ragged:
             if t.numel() != int(self.offsets[-1]):
                 raise ValueError(f"packed inputs must hold {int(self.offsets[-1])} elements")
         self.build(dev)
-        u = out if out is not None else torch.empty_like(gx)
+        u = check_out(out, gx.shape, dev, (gx, gy)) if out is not None else torch.empty_like(gx)
+        need = self.workspace_size()
         if workspace is None:
-            need = self.workspace_size()
-            if self._ws is None or self._ws.numel() < need or self._ws.device != dev:
+            if self._ws is None or _nbytes(self._ws) < need or self._ws.device != dev:
                 self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
             workspace = self._ws
+        else:
+            check_workspace(workspace, need, dev, (gx, gy, u))
         with torch.cuda.device(dev):
             _check(fn(self._h, gx.data_ptr(), gy.data_ptr(), u.data_ptr(), workspace.data_ptr(),
-                      workspace.numel() * workspace.element_size(), _stream_ptr(torch, dev, stream)),
+                      _nbytes(workspace), _stream_ptr(torch, dev, stream)),
                    name)
         return u
 

@@ -123,7 +123,6 @@ void fill_colconst(const gfc_plan_s& p, const ColGeom& g, bool forward,
 
 namespace {
 
-
 // launch geometry that follows from the sizes and the tunable parameters
 // Row bins handed to the column pass in split form. The rounding of the row FFT in bins
 // l > K reaches the solution amplified by about N / (K M) (the column frequency 0 carries
@@ -312,6 +311,14 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
     cs2pi(long(l) * p->c0, N, c, s);
     dsh[l] = f2{float(c), float(-s)};    // e^{-2 pi i l c0 / N}
   }
+  // float64 w_N^m = e^{-2 pi i m / N}, m < N: direct sums of a given Laplacian's low bins
+  std::vector<double> twD(size_t(2) * N);
+  for (int m = 0; m < N; ++m) {
+    double c, sn;
+    cs2pi(m, N, c, sn);
+    twD[2 * size_t(m)] = c;
+    twD[2 * size_t(m) + 1] = -sn;
+  }
   std::vector<ColConst> ccf, ccb;
   fill_colconst(*p, p->gf, true, ccf, 1, 0);
   fill_colconst(*p, p->gb, false, ccb, 1, 0);
@@ -325,6 +332,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   const size_t o_dsh = off; off = align256(off + dsh.size() * sizeof(f2));
   const size_t o_ccf = off; off = align256(off + ccf.size() * sizeof(ColConst));
   const size_t o_ccb = off; off = align256(off + ccb.size() * sizeof(ColConst));
+  const size_t o_twD = off; off = align256(off + twD.size() * sizeof(double));
   std::vector<unsigned char> host(off, 0);
   std::memcpy(host.data() + o_twA, twA.data(), twA.size() * sizeof(f2));
   std::memcpy(host.data() + o_twB, twB.data(), twB.size() * sizeof(f2));
@@ -334,6 +342,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   std::memcpy(host.data() + o_dsh, dsh.data(), dsh.size() * sizeof(f2));
   std::memcpy(host.data() + o_ccf, ccf.data(), ccf.size() * sizeof(ColConst));
   std::memcpy(host.data() + o_ccb, ccb.data(), ccb.size() * sizeof(ColConst));
+  std::memcpy(host.data() + o_twD, twD.data(), twD.size() * sizeof(double));
 
   void* d = nullptr;
   if (hipMalloc(&d, off) != hipSuccess) return GFC_E_OOM;
@@ -353,6 +362,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   p->dshift = reinterpret_cast<f2*>(base + o_dsh);
   p->ccf = reinterpret_cast<ColConst*>(base + o_ccf);
   p->ccb = reinterpret_cast<ColConst*>(base + o_ccb);
+  p->twD = reinterpret_cast<double*>(base + o_twD);
   (void)hipGetDevice(&p->device);
   if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -438,7 +448,23 @@ static gfc_status solve_forward(gfc_plan_t p, const float* gx, const float* gy, 
     if (st != GFC_OK) return st;
   }
   if (edit == kInLaplacian) {
-    st = hip_status(launch_sb_prefix(SB, p->H, p->KP, f.img_sb, B, s));
+    LapLowArgs la{};
+    la.L = C;
+    la.twD = p->twD;
+    la.Lh = reinterpret_cast<double*>(ws + w.lap);
+    la.T1 = T;
+    la.SB = SB;
+    la.H = p->H;
+    la.W = p->W;
+    la.N = p->N;
+    la.K = p->K;
+    la.NHP = p->NHP;
+    la.KP = p->KP;
+    la.img_L = (long long)(p->H + 1) * (p->W + 1);
+    la.img_lh = (long long)(p->H + 1) * (p->K + 1) * 2;
+    la.img_t1 = f.img_t1;
+    la.img_sb = f.img_sb;
+    st = hip_status(launch_lap_low(la, B, s));
     if (st != GFC_OK) return st;
   }
   {

@@ -305,7 +305,8 @@ __global__ void __launch_bounds__(kColMaxThreads) k_col_fwd(ColFwdArgs p) {
 // images (threads past an image's C * nseg idle through the barriers)
 template <int LMAX, bool LOWTILE, bool TAIL>
 __global__ void __launch_bounds__(kColMaxThreads)
-k_col_fwd_rg(RgBase base, const RgCol* tab, const RgItem* items) {
+k_col_fwd_rg(const RgBase* basep, const RgCol* tab, const RgItem* items) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
   extern __shared__ dc s_mem[];
   const RgItem it = items[blockIdx.x];
   const RgCol& e = tab[it.img];
@@ -580,7 +581,7 @@ hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t
 
 namespace {
 template <int LMAX, bool TAIL>
-void launch_rg_tiles(const RgBase& base, const RgCol* tab, const RgItem* low, int nlow,
+void launch_rg_tiles(const RgBase* base, const RgCol* tab, const RgItem* low, int nlow,
                      const RgItem* rest, int nrest, int threads, size_t shm, hipStream_t s) {
   if (nlow > 0)
     hipLaunchKernelGGL((k_col_fwd_rg<LMAX, true, TAIL>), dim3(nlow), dim3(threads), shm, s,
@@ -591,7 +592,7 @@ void launch_rg_tiles(const RgBase& base, const RgCol* tab, const RgItem* low, in
 }
 }  // namespace
 
-hipError_t launch_col_fwd_rg(const RgBase& base, const RgCol* tab, const RgItem* low,
+hipError_t launch_col_fwd_rg(const RgBase* base, const RgCol* tab, const RgItem* low,
                              int nlow, const RgItem* rest, int nrest, int Lseg, bool tail,
                              int threads, size_t shm, hipStream_t s) {
   if (threads < 64 || threads > kColMaxThreads || threads % 64) return hipErrorInvalidValue;

@@ -61,52 +61,10 @@ hipError_t launch_color_apply(float* u, const double* mom, int nparts, const flo
 
 }  // namespace gfc
 
-namespace gfc {
-
-// Running sums of the DC column of the split side array (Laplacian input): one workgroup per
-// image scans its H rows in chunks of kScanThreads, float64 Hillis-Steele scans in LDS with a
-// carry between chunks (fixed order).
-constexpr int kScanThreads = 256;
-
-__global__ void __launch_bounds__(kScanThreads)
-k_sb_prefix(f2* SB, int H, int KP, long long img_sb) {
-  __shared__ double sx[kScanThreads], sy[kScanThreads];
-  const int t = threadIdx.x;
-  f2* base = SB + blockIdx.x * img_sb;
-  double cx = 0.0, cy = 0.0;
-  for (int y0 = 0; y0 < H; y0 += kScanThreads) {
-    const int y = y0 + t;
-    double vx = 0.0, vy = 0.0;
-    if (y < H) {
-      const f2 v = base[(long long)y * KP];
-      vx = v.x;
-      vy = v.y;
-    }
-    sx[t] = vx;
-    sy[t] = vy;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-      const double ax = t >= d ? sx[t - d] : 0.0, ay = t >= d ? sy[t - d] : 0.0;
-      __syncthreads();
-      sx[t] += ax;
-      sy[t] += ay;
-      __syncthreads();
-    }
-    if (y < H) base[(long long)y * KP] = f2{float(cx + sx[t]), float(cy + sy[t])};
-    cx += sx[kScanThreads - 1];
-    cy += sy[kScanThreads - 1];
-    __syncthreads();
-  }
-}
-
-hipError_t launch_sb_prefix(f2* SB, int H, int KP, long long img_sb, int B, hipStream_t s) {
-  hipLaunchKernelGGL(k_sb_prefix, dim3(B), dim3(kScanThreads), 0, s, SB, H, KP, img_sb);
-  return hipGetLastError();
-}
-
-}  // namespace gfc
 
 namespace gfc {
+
+constexpr int kScanThreads = 256;  // threads of the small per-plane kernels below
 
 // Volumes: the split bins l <= K of the column input are a = (1 - w_N^l) Ex^ + (1 - w_P^kz) Ez^
 // and b = Ey^ (the y difference is applied inside the column recursion). T holds the z

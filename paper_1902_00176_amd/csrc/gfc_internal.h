@@ -70,9 +70,23 @@ struct RowInvArgs {
 // Bins kLowBins < l <= K of T1 and SB in the split form, as direct float32 sums over the
 // (edited) gradient rows; run after the row pass on the same stream. No-op for K <= kLowBins.
 hipError_t launch_low_ext(const RowFwdArgs& a, int B, hipStream_t s);
-// Laplacian input: SB[y][0] <- sum_{y' <= y} SB[y'][0] for y in [0, H) of every image, so the
-// column pass's split form (1 - S) b reproduces the DC column of L (float64 running sums).
-hipError_t launch_sb_prefix(f2* SB, int H, int KP, long long img_sb, int B, hipStream_t s);
+// Laplacian input, bins l <= K: the column pass takes these bins in the split form
+// a + (1 - S) b. For a given L they are written as b[y, l] = P[y, l] (y < H), a[y, l] = 0 for
+// y < H and a[H, l] = P[H, l], with P[y, l] = sum_{y' <= y} L^[y', l] the running sum over
+// rows of the row spectra; then a + (1 - S) b = L^ row by row, and the column sums, which
+// the Green's function amplifies most, are P's last row: a single value, never a difference
+// of rounded ones. L^[y, l] are direct sums with float64 twiddles and accumulation, P is a
+// float64 scan (fixed order); each is rounded once to float32.
+struct LapLowArgs {
+  const float* L;     // [B][H+1][W+1]
+  const double* twD;  // [N][2]: w_N^m = (cos, -sin)(2 pi m / N), float64
+  double* Lh;         // [B][H+1][K+1][2]: L^[y, l] (workspace)
+  f2* T1;             // [B][H+1][NHP]
+  f2* SB;             // [B][H][KP]
+  int H, W, N, K, NHP, KP;
+  long long img_L, img_lh, img_t1, img_sb;
+};
+hipError_t launch_lap_low(const LapLowArgs& a, int B, hipStream_t s);
 
 // Colour correction of eq. (25) in place on u [B][npix]: every workgroup of image b reduces
 // that image's nparts moment pairs in a fixed order, then u <- (u - mean) * I_std[b] / std + I_mean[b].
@@ -185,6 +199,8 @@ struct RgBase {
   float* u;
   unsigned char* ws;
 };
+// The ragged kernels read the bases from a device slot, written on the launch stream by
+// launch_set_base just before them: a captured graph then serves any buffer addresses.
 struct RgRowFwd {
   RowFwdArgs a;
   long long in, t, side;
@@ -227,16 +243,16 @@ struct RowKernels {
   hipError_t (*inv)(const RowInvArgs&, int B, hipStream_t);
   hipError_t (*bfwd)(const RowBwdFwdArgs&, int B, hipStream_t);
   hipError_t (*binv)(const RowBwdInvArgs&, int B, hipStream_t);
-  hipError_t (*rg_fwd)(const RgBase&, const RgRowFwd*, const RgItem*, int nitems, bool half,
+  hipError_t (*rg_fwd)(const RgBase*, const RgRowFwd*, const RgItem*, int nitems, bool half,
                        hipStream_t);
-  hipError_t (*rg_inv)(const RgBase&, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*rg_inv)(const RgBase*, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
 };
 const RowKernels* find_row_kernels(int N);
 // ragged launches that cover several row lengths of one workgroup size (half support only)
 struct RgMulti {
   int id;  // distinct per group of lengths
-  hipError_t (*fwd)(const RgBase&, const RgRowFwd*, const RgItem*, int nitems, hipStream_t);
-  hipError_t (*inv)(const RgBase&, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*fwd)(const RgBase*, const RgRowFwd*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*inv)(const RgBase*, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
 };
 const RgMulti* find_rg_multi(int N);
 int row_kernel_count();
@@ -247,12 +263,12 @@ hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t
 hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
 // ragged forward column pass: items of tiles holding columns l <= K and of the others,
 // one workgroup shape (threads, LDS bytes) for all images, rows per segment Lseg
-hipError_t launch_col_fwd_rg(const RgBase& base, const RgCol* tab, const RgItem* low,
+hipError_t launch_col_fwd_rg(const RgBase* base, const RgCol* tab, const RgItem* low,
                              int nlow, const RgItem* rest, int nrest, int Lseg, bool tail,
                              int threads, size_t shm, hipStream_t s);
 constexpr int kColMaxThreads = 1024;  // largest column-pass workgroup
 // ragged low-bin extension: items (image, row y <= H) of the images whose plan has K > kLowBins
-hipError_t launch_low_ext_rg(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+hipError_t launch_low_ext_rg(const RgBase* base, const RgRowFwd* tab, const RgItem* items,
                              int nitems, hipStream_t s);
 
 }  // namespace gfc

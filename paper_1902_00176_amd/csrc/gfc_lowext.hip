@@ -109,7 +109,8 @@ __global__ void __launch_bounds__(64 * kExtWaves) k_low_ext(RowFwdArgs p) {
 }
 
 __global__ void __launch_bounds__(64 * kExtWaves)
-k_low_ext_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
+k_low_ext_rg(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
   const RgItem it = items[blockIdx.x];
   const RgRowFwd& e = tab[it.img];
   RowFwdArgs p = e.a;
@@ -142,12 +143,123 @@ hipError_t launch_low_ext(const RowFwdArgs& a, int B, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_low_ext_rg(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+hipError_t launch_low_ext_rg(const RgBase* base, const RgRowFwd* tab, const RgItem* items,
                              int nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   // every image of the list has K <= kMaxLowBins; groups past an image's K return at once
   k_low_ext_rg<<<dim3(unsigned(nitems), unsigned(kMaxGroups)), dim3(64 * kExtWaves), 0, s>>>(
       base, tab, items);
+  return hipGetLastError();
+}
+
+}  // namespace gfc
+
+// ---------------------------------------------------------------------------------------
+// A given Laplacian (Algorithm B's input): its lowest row bins in the split form a + (1 - S) b
+// of the column pass. b[y, l] = P[y, l] for y < H, a[y, l] = 0 for y < H, a[H, l] = P[H, l],
+// where P[y, l] = sum_{y' <= y} L^[y', l]: then a + (1 - S) b is L^ on every row, and the
+// sum over the rows (the column frequency 0, which the Green's function amplifies most) is
+// the one value P[H, l] instead of a difference of rounded values. An FFT of L in float32
+// leaves an error of the size of |L| in these bins, where the true values nearly cancel.
+namespace gfc {
+namespace {
+
+constexpr int kLapWaves = 4;  // rows per workgroup of k_lap_rows, one per wavefront
+constexpr int kLapBins = 4;   // bins summed per sweep over a row
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// L^[y, l] for l <= K of one row per wavefront: lane j takes x = j, j + 64, ...; the
+// twiddle w_N^(l x) advances by w_N^(64 l) in float64 (at most 64 steps per lane).
+__global__ void __launch_bounds__(64 * kLapWaves) k_lap_rows(LapLowArgs a) {
+  const int lane = int(threadIdx.x) & 63;
+  const int y = int(blockIdx.x) * kLapWaves + (int(threadIdx.x) >> 6);
+  const int b = blockIdx.y;
+  if (y > a.H) return;  // no workgroup barrier below
+  const float* row = a.L + b * a.img_L + (long long)y * (a.W + 1);
+  double* out = a.Lh + b * a.img_lh + (long long)y * (a.K + 1) * 2;
+  for (int l0 = 0; l0 <= a.K; l0 += kLapBins) {
+    double ar[kLapBins], ai[kLapBins], wr[kLapBins], wi[kLapBins], sr[kLapBins], si[kLapBins];
+#pragma unroll
+    for (int i = 0; i < kLapBins; ++i) {
+      const int l = l0 + i <= a.K ? l0 + i : 0;
+      const int m = int((long long)l * lane % a.N), d = int((long long)l * 64 % a.N);
+      ar[i] = ai[i] = 0.0;
+      wr[i] = a.twD[2 * m];
+      wi[i] = a.twD[2 * m + 1];
+      sr[i] = a.twD[2 * d];
+      si[i] = a.twD[2 * d + 1];
+    }
+    for (int x = lane; x <= a.W; x += 64) {
+      const double v = row[x];
+#pragma unroll
+      for (int i = 0; i < kLapBins; ++i) {
+        ar[i] = __builtin_fma(v, wr[i], ar[i]);
+        ai[i] = __builtin_fma(v, wi[i], ai[i]);
+        const double nr = __builtin_fma(wr[i], sr[i], -wi[i] * si[i]);
+        wi[i] = __builtin_fma(wr[i], si[i], wi[i] * sr[i]);
+        wr[i] = nr;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kLapBins; ++i) {
+      const double sr_ = wave_sum(ar[i]), si_ = wave_sum(ai[i]);
+      if (lane == 0 && l0 + i <= a.K) {
+        out[2 * (l0 + i)] = sr_;
+        out[2 * (l0 + i) + 1] = si_;
+      }
+    }
+  }
+}
+
+// P[y, l] = running sum of L^[y, l] over y (one wavefront per (l, image), chunks of 64 rows,
+// float64 Hillis-Steele scans with a carry between chunks: a fixed order), then the split
+// form: SB[y, l] = P[y, l] and T1[y, l] = 0 for y < H, T1[H, l] = P[H, l].
+__global__ void __launch_bounds__(64) k_lap_prefix(LapLowArgs a) {
+  const int lane = threadIdx.x;
+  const int l = blockIdx.x, b = blockIdx.y;
+  const double* in = a.Lh + b * a.img_lh;
+  f2* t1 = a.T1 + b * a.img_t1;
+  f2* sb = a.SB + b * a.img_sb;
+  double cr = 0.0, ci = 0.0;
+  for (int y0 = 0; y0 <= a.H; y0 += 64) {
+    const int y = y0 + lane;
+    double vr = 0.0, vi = 0.0;
+    if (y <= a.H) {
+      vr = in[((long long)y * (a.K + 1) + l) * 2];
+      vi = in[((long long)y * (a.K + 1) + l) * 2 + 1];
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double ur = __shfl_up(vr, d, 64), ui = __shfl_up(vi, d, 64);
+      if (lane >= d) {
+        vr += ur;
+        vi += ui;
+      }
+    }
+    const double pr = cr + vr, pi = ci + vi;
+    if (y < a.H) {
+      sb[(long long)y * a.KP + l] = f2{float(pr), float(pi)};
+      t1[(long long)y * a.NHP + l] = f2{0.f, 0.f};
+    } else if (y == a.H) {
+      t1[(long long)y * a.NHP + l] = f2{float(pr), float(pi)};
+    }
+    cr = __shfl(pr, 63, 64);
+    ci = __shfl(pi, 63, 64);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_lap_low(const LapLowArgs& a, int B, hipStream_t s) {
+  if (a.K < 0 || a.K >= a.KP || a.H < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lap_rows, dim3(unsigned((a.H + 1 + kLapWaves - 1) / kLapWaves), unsigned(B)),
+                     dim3(64 * kLapWaves), 0, s, a);
+  hipLaunchKernelGGL(k_lap_prefix, dim3(unsigned(a.K + 1), unsigned(B)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

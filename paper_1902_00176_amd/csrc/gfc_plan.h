@@ -42,6 +42,7 @@ struct gfc_plan_s {
   void* dmem = nullptr;
   gfc::f2 *twA = nullptr, *twB = nullptr, *twL = nullptr, *twX = nullptr, *sxm = nullptr,
           *dshift = nullptr;
+  double* twD = nullptr;  // [N][2] float64 w_N^m (direct sums of a given Laplacian's low bins)
   gfc::ColConst *ccf = nullptr, *ccb = nullptr;
   // a side stream for the forward column pass's low tiles, joined back with two events
   hipStream_t side = nullptr;
@@ -60,9 +61,9 @@ inline int inv_groups(const gfc_plan_s* p) {
 }
 
 // workspace of a batch: spectra T, side arrays (SB forward / SD backward), reductions,
-// moment sums of the colour correction
+// moment sums of the colour correction, float64 low-bin row sums of a given Laplacian
 struct WsLayout {
-  size_t t, side, red, mom, total;
+  size_t t, side, red, mom, lap, total;
 };
 inline WsLayout ws_layout(const gfc_plan_s* p, int B) {
   WsLayout w{};
@@ -76,8 +77,10 @@ inline WsLayout ws_layout(const gfc_plan_s* p, int B) {
   w.t = 0;
   w.side = align256(tbytes);
   w.red = w.side + align256(std::max(sb, sd));
+  const size_t pl = Bz * size_t(p->H + 1) * size_t(p->K + 1) * 2 * sizeof(double);
   w.mom = w.red + align256(std::max(pf, ps));
-  w.total = w.mom + align256(pm);
+  w.lap = w.mom + align256(pm);
+  w.total = w.lap + align256(pl);
   return w;
 }
 

@@ -14,8 +14,9 @@
 // streams never wait for each other, so one stream's column pass overlaps another's row
 // launches. Work items are ordered largest image first so the small ones fill the tail of
 // a launch.
-// The whole sequence is captured once into a HIP graph and replayed by every later call
-// with the same buffers. Per image the arithmetic is the plain path's, so a ragged solve
+// The whole sequence is captured once into a HIP graph and replayed by every later call: the
+// kernels read the buffer bases from a device slot that each call fills first (a one-thread
+// kernel on the caller's stream), so new addresses need no new graph. Per image the arithmetic is the plain path's, so a ragged solve
 // equals solving each image with its plan (gfc_ragged_solve_sequential).
 #include <hip/hip_runtime.h>
 
@@ -84,14 +85,24 @@ struct gfc_ragged_s {
   hipStream_t side[kRgStreams - 1] = {};
   hipEvent_t ev[4 * kRgStreams] = {};
   hipStream_t cap = nullptr;
+  RgBase* dbase = nullptr;  // device slot the kernels read the buffer bases from
+  // the launch sequence, captured once: it reads the bases from dbase, so it serves every
+  // call; `done` is recorded after each launch (destroy waits for it)
   hipGraphExec_t exec = nullptr;
-  RgBase cached{};
+  hipEvent_t done = nullptr;
 };
 
 namespace {
 
+__global__ void k_set_base(RgBase* slot, RgBase v) {
+  if (threadIdx.x == 0) *slot = v;
+}
+
 void release(gfc_ragged_s* r) {
+  // the graph may still run on a caller's stream: wait for its last launch first
+  if (r->done) (void)hipEventSynchronize(r->done);
   if (r->exec) (void)hipGraphExecDestroy(r->exec);
+  if (r->done) (void)hipEventDestroy(r->done);
   for (auto& e : r->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& s : r->side)
@@ -104,7 +115,7 @@ void release(gfc_ragged_s* r) {
 
 // Enqueue the three passes of every stream's images on `main` and the side streams, joined
 // back to `main`.
-gfc_status enqueue(gfc_ragged_s* r, const RgBase& base, hipStream_t main) {
+gfc_status enqueue(gfc_ragged_s* r, const RgBase* base, hipStream_t main) {
   static_assert(kRgStreams == 4, "one Lane per stream");
   hipStream_t st[kRgStreams] = {main, r->side[0], r->side[1], r->side[2]};
   auto fork = [&](int k) -> bool {  // side streams wait for main
@@ -384,6 +395,8 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
   o = align256(o + ti.size() * sizeof(RgRowInv));
   const size_t o_it = o;
   o = align256(o + items.size() * sizeof(RgItem));
+  const size_t o_base = o;
+  o = align256(o + sizeof(RgBase));
   std::vector<unsigned char> host(std::max<size_t>(o, 256), 0);
   if (!tf.empty()) std::memcpy(host.data() + o_f, tf.data(), tf.size() * sizeof(RgRowFwd));
   if (!tc.empty()) std::memcpy(host.data() + o_c, tc.data(), tc.size() * sizeof(RgCol));
@@ -403,12 +416,14 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
   r->tab_c = reinterpret_cast<RgCol*>(base + o_c);
   r->tab_i = reinterpret_cast<RgRowInv*>(base + o_i);
   r->items = reinterpret_cast<RgItem*>(base + o_it);
+  r->dbase = reinterpret_cast<RgBase*>(base + o_base);
 
   for (auto& st : r->side)
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return GFC_E_HIP;
   if (hipStreamCreateWithFlags(&r->cap, hipStreamNonBlocking) != hipSuccess) return GFC_E_HIP;
   for (auto& e : r->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return GFC_E_HIP;
+  if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) return GFC_E_HIP;
   (void)hipGetDevice(&r->device);
   r->built = true;
   return GFC_OK;
@@ -442,19 +457,15 @@ gfc_status gfc_ragged_solve(gfc_ragged_t r, const float* gx, const float* gy, fl
   if (st != GFC_OK || r->B == 0) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const RgBase base{gx, gy, u, static_cast<unsigned char*>(workspace)};
-  if (r->flags & GFC_RAGGED_NO_GRAPH) return enqueue(r, base, s);
-  const bool same = r->exec && r->cached.gx == gx && r->cached.gy == gy && r->cached.u == u &&
-                    r->cached.ws == base.ws;
-  if (!same) {
-    if (r->exec) {
-      // the previous graph may still be running on the caller's stream
-      if (hipStreamSynchronize(s) != hipSuccess) return GFC_E_HIP;
-      (void)hipGraphExecDestroy(r->exec);
-      r->exec = nullptr;
-    }
+  // the bases of this call into the device slot, ahead of the passes on the same stream
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, r->dbase, base);
+  if (hipGetLastError() != hipSuccess) return GFC_E_HIP;
+  if (r->flags & GFC_RAGGED_NO_GRAPH) return enqueue(r, r->dbase, s);
+  if (!r->exec) {
+    // first call: capture the launch sequence (it reads the bases from the slot)
     if (hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return GFC_E_HIP;
-    st = enqueue(r, base, r->cap);
+    st = enqueue(r, r->dbase, r->cap);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(r->cap, &graph);
     if (st != GFC_OK || e != hipSuccess || !graph) {
@@ -467,9 +478,9 @@ gfc_status gfc_ragged_solve(gfc_ragged_t r, const float* gx, const float* gy, fl
       r->exec = nullptr;
       return GFC_E_HIP;
     }
-    r->cached = base;
   }
-  return hip_status(hipGraphLaunch(r->exec, s));
+  if (hipGraphLaunch(r->exec, s) != hipSuccess) return GFC_E_HIP;
+  return hip_status(hipEventRecord(r->done, s));
 }
 
 gfc_status gfc_ragged_solve_sequential(gfc_ragged_t r, const float* gx, const float* gy,

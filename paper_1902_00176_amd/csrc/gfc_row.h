@@ -669,9 +669,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     for (int i = 0; i < C::NI; ++i) {
       const int l = lane + C::G * i;
       if constexpr (FULLBINS) {
-        // every bin of L^ goes to T1. Laplacian input: the split side array gets (0 for
-        // l > 0 and) the DC bin, turned into its running sum over the rows by
-        // launch_sb_prefix; volumes build theirs after the z transform
+        // every bin of L^ goes to T1. A given Laplacian's bins l <= K are then replaced by
+        // their split form (launch_lap_low); volumes build theirs after the z transform
         if (ok && l < C::NH) {
           const int m = (l == 0) ? 0 : C::N - l;
           const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
@@ -679,11 +678,6 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
           const cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
           bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
           if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
-          if (EDIT == kInLaplacian && l <= p.K) {
-            const bool dc = l == 0;
-            if (y0 < p.H) bst2(rSB, dc ? A.x : 0.f, dc ? A.y : 0.f, (y0 * p.KP + l) * 8, 0);
-            if (y0 + 1 < p.H) bst2(rSB, dc ? B.x : 0.f, dc ? B.y : 0.f, ((y0 + 1) * p.KP + l) * 8, 0);
-          }
         }
       } else if (ok && l < C::NH && (l == 0 || l > KL)) {
         const int m = (l == 0) ? 0 : C::N - l;
@@ -737,7 +731,8 @@ k_row_fwd(RowFwdArgs p) {
 // ragged batches: one work item (image, block) per workgroup; pointers rebased per image
 template <int N1, int N2, int SLOTS, int NB>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_fwd_rg(RgBase base, const RgRowFwd* tab, const RgItem* items) {
+k_row_fwd_rg(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
   const RgItem it = items[blockIdx.x];
   const RgRowFwd& e = tab[it.img];
   RowFwdArgs p = e.a;
@@ -851,7 +846,8 @@ k_row_inv(RowInvArgs p) {
 
 template <int N1, int N2, int SLOTS>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_inv_rg(RgBase base, const RgRowInv* tab, const RgItem* items) {
+k_row_inv_rg(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
   const RgItem it = items[blockIdx.x];
   const RgRowInv& e = tab[it.img];
   RowInvArgs p = e.a;
@@ -1076,7 +1072,7 @@ struct RowLaunch {
     return hipGetLastError();
   }
   // half: every image of the launch has 2 W <= N
-  static hipError_t rg_fwd(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+  static hipError_t rg_fwd(const RgBase* base, const RgRowFwd* tab, const RgItem* items,
                            int nitems, bool half, hipStream_t s) {
     if (half)
       hipLaunchKernelGGL((k_row_fwd_rg<N1, N2, SLOTS, NB_HALF>), dim3(nitems),
@@ -1086,7 +1082,7 @@ struct RowLaunch {
                          0, s, base, tab, items);
     return hipGetLastError();
   }
-  static hipError_t rg_inv(const RgBase& base, const RgRowInv* tab, const RgItem* items,
+  static hipError_t rg_inv(const RgBase* base, const RgRowInv* tab, const RgItem* items,
                            int nitems, hipStream_t s) {
     hipLaunchKernelGGL((k_row_inv_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
                        base, tab, items);
@@ -1117,7 +1113,8 @@ constexpr int cmax_n(int a, int b, T... r) { return cmax_n(cmax(a, b), r...); }
 
 template <class L0, class... Ls>
 __global__ void __launch_bounds__(L0::THREADS)
-k_row_fwd_rgm(RgBase base, const RgRowFwd* tab, const RgItem* items) {
+k_row_fwd_rgm(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
   static_assert(((Ls::THREADS == L0::THREADS) && ...), "one workgroup size per launch");
   constexpr int NL = cmax_n(L0::FWD_LDS, Ls::FWD_LDS...);
   __shared__ float lds[NL];
@@ -1138,7 +1135,8 @@ k_row_fwd_rgm(RgBase base, const RgRowFwd* tab, const RgItem* items) {
 
 template <class L0, class... Ls>
 __global__ void __launch_bounds__(L0::THREADS)
-k_row_inv_rgm(RgBase base, const RgRowInv* tab, const RgItem* items) {
+k_row_inv_rgm(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
   constexpr int NL = cmax_n(L0::INV_LDS, Ls::INV_LDS...);
   __shared__ float lds[NL];
   const RgItem it = items[blockIdx.x];
@@ -1155,13 +1153,13 @@ k_row_inv_rgm(RgBase base, const RgRowInv* tab, const RgItem* items) {
 
 template <class L0, class... Ls>
 struct RowMulti {
-  static hipError_t fwd(const RgBase& base, const RgRowFwd* tab, const RgItem* items,
+  static hipError_t fwd(const RgBase* base, const RgRowFwd* tab, const RgItem* items,
                         int nitems, hipStream_t s) {
     hipLaunchKernelGGL((k_row_fwd_rgm<L0, Ls...>), dim3(nitems), dim3(L0::THREADS), 0, s, base,
                        tab, items);
     return hipGetLastError();
   }
-  static hipError_t inv(const RgBase& base, const RgRowInv* tab, const RgItem* items,
+  static hipError_t inv(const RgBase* base, const RgRowInv* tab, const RgItem* items,
                         int nitems, hipStream_t s) {
     hipLaunchKernelGGL((k_row_inv_rgm<L0, Ls...>), dim3(nitems), dim3(L0::THREADS), 0, s, base,
                        tab, items);

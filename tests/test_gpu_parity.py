@@ -401,3 +401,27 @@ def test_one_plan_from_several_host_threads():
     for t in ts:
         t.join()
     assert not errors, errors
+
+
+def test_bad_outputs_and_workspaces_raise_before_any_launch():
+    """A caller's `out` or workspace on the wrong device, too small, of the wrong shape or
+    aliasing an input is refused by the binding (no pointer reaches a kernel)."""
+    p = gfc.Plan(20, 30, tuned=False)
+    gx = torch.zeros(2, 20, 30, device="cuda")
+    gy = torch.zeros(2, 20, 30, device="cuda")
+    need = p.workspace_size(2)
+    with pytest.raises(ValueError):
+        p.solve(gx, gy, out=torch.empty(2, 20, 30))  # host memory
+    with pytest.raises(ValueError):
+        p.solve(gx, gy, out=torch.empty(1, 20, 30, device="cuda"))
+    with pytest.raises(ValueError):
+        p.solve(gx, gy, out=gx)
+    with pytest.raises(ValueError):
+        p.solve(gx, gy, workspace=torch.empty(need - 1, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        p.solve(gx, gy, workspace=torch.empty(need, dtype=torch.uint8))
+    # a float32 workspace of enough bytes is accepted (bytes, not elements, are counted)
+    ws = torch.empty((need + 3) // 4, dtype=torch.float32, device="cuda")
+    u = p.solve(gx + 1e-3, gy, workspace=ws)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(u).all())

@@ -108,6 +108,23 @@ def test_ragged_graph_replays_and_recaptures():
     assert torch.equal(out2, ref)
 
 
+def test_ragged_alternating_outputs_replay_cached_graphs():
+    """Outputs at alternating addresses (a caller that keeps the previous result): each call
+    replays or captures a graph without waiting on the GPU, and every result is exact."""
+    _say("ragged: alternating output buffers")
+    r, _, gx, gy = _run_mixed()
+    ref = r.solve_sequential(gx, gy)
+    torch.cuda.synchronize()
+    outs = [torch.empty_like(gx) for _ in range(6)]
+    for rep in range(3):
+        for o in outs:  # six address sets: more than the graphs kept, so some are evicted
+            o.fill_(float("nan"))
+            r.solve(gx, gy, out=o)
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert torch.equal(o, ref), k
+
+
 def test_ragged_empty_batch():
     r = gfc.Ragged([])
     dev = torch.device("cuda:0")
@@ -118,8 +135,10 @@ def test_ragged_empty_batch():
 
 
 def test_ragged_uneven_batch_full_size():
-    """The uneven-size workload: 200 images, H, W ~ U{64..1024}, default tori (128..2048)."""
-    _say("ragged 200 images (64..1024): graph vs sequential on all, oracle on a sample")
+    """The uneven-size workload: 200 images, H, W ~ U{64..1024}, default tori (128..2048),
+    in the launch configuration the benchmark times (one graph replay). Every image is
+    compared with the float64 oracle, and the whole batch with the per-image plain solves."""
+    _say("ragged 200 images (64..1024): graph vs sequential and every image vs the oracle")
     sizes = synth.ragged_sizes()
     pairs = synth.make_ragged(sizes=sizes)
     r = gfc.Ragged(sizes)
@@ -131,15 +150,15 @@ def test_ragged_uneven_batch_full_size():
     torch.cuda.synchronize()
     assert torch.equal(u, us)
     assert bool(torch.isfinite(u).all())
-    areas = [h * w for h, w in sizes]
-    sample = sorted({int(np.argmax(areas)), int(np.argmin(areas)), 17})
-    ul = r.unpack(u)
-    for k in sample:
+    ul = [t.cpu().numpy() for t in r.unpack(u)]
+    worst = (0.0, -1)
+    for k in range(len(sizes)):
         H, W, M, N = r.sizes[k]
         ref = O.solve_fft(pairs[k][0], pairs[k][1], M, N)
-        e = rel_l2(ul[k].cpu().numpy(), ref)
-        _say(f"  image {k} {H}x{W} on {M}x{N}: rel L2 {e:.2e}")
-        assert e <= TOL, (k, e)
+        e = rel_l2(ul[k], ref)
+        worst = max(worst, (e, k))
+        assert e <= TOL, (k, (H, W, M, N), e)
+    _say(f"  worst image {worst[1]} {r.sizes[worst[1]]}: rel L2 {worst[0]:.2e}")
 
 
 def test_ragged_solve_helper():
