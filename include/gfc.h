@@ -114,6 +114,22 @@ gfc_status gfc_solve_batch(gfc_plan_t p, const float* gx, const float* gy, float
                            void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): gfc_solve_batch with no workspace argument. The
+ * workspace is a fixed array of GFC_NOALLOC_SCRATCH_BYTES inside the library, one copy per
+ * GPU, held until the process ends; the call itself allocates nothing (its first call on a
+ * GPU looks the array's device address up once). Same kernels and results as
+ * gfc_solve_batch, bit for bit. GFC_E_WORKSPACE when the workspace of (p, B)
+ * (gfc_workspace_size) exceeds GFC_NOALLOC_SCRATCH_BYTES, e.g. 801 x 1200 images on their
+ * default torus take about 8.0 MiB each, so at most 7 per call. All calls on one GPU share
+ * its array: calls that may overlap on one GPU (several streams or host threads) race on it
+ * and must be serialised by the caller; calls in order on one stream are safe.
+ */
+#define GFC_NOALLOC_SCRATCH_BYTES (64u << 20)
+gfc_status gfc_solve_batch_noalloc(gfc_plan_t p, const float* gx, const float* gy, float* u,
+                                   int B, void* stream);
+
+/*
  * Forward solve followed by the colour-preserving correction of eq. (25) (Sec. 3.2.2):
  *   u = (u_c - mean(u_c)) * I_std[b] / std(u_c) + I_mean[b]   over each H x W image,
  * where u_c is what gfc_solve_batch returns and I_mean, I_std ([B] float32, device) are the

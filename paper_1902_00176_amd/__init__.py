@@ -62,6 +62,8 @@ def lib():
             L.gfc_solve_edit.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, vp, vp, vp, i, vp,
                                          sz, vp]
             L.gfc_solve_laplacian.argtypes = [vp, vp, vp, i, vp, sz, vp]
+            L.gfc_solve_batch_noalloc.argtypes = [vp, vp, vp, vp, i, vp]
+            L.gfc_solve_batch_noalloc.restype = ctypes.c_int
             L.gfc_plan3_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, i, i, u]
             L.gfc_plan3_get.argtypes = [vp, ip, ip, ip, ip, ip, ip]
             L.gfc_green_build3.argtypes = [vp, vp]

@@ -180,7 +180,8 @@ def build(lengths=None, jobs=None, verbose=True, force=False):
     if os.path.isdir(BUILD) and force:
         shutil.rmtree(BUILD)
     os.makedirs(BUILD, exist_ok=True)
-    units = ("gfc_api.hip", "gfc_col.hip", "gfc_ragged.hip", "gfc_color.hip", "gfc_lowext.hip")
+    units = ("gfc_api.hip", "gfc_col.hip", "gfc_ragged.hip", "gfc_color.hip", "gfc_lowext.hip",
+             "gfc_noalloc.hip")
     srcs = [os.path.join(CSRC, f) for f in units] + generate(lengths)
     headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     headers.append(os.path.join(INCLUDE, "gfc.h"))
