@@ -91,9 +91,17 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream);
  *                       direct-sum pass over the gradient for l in (4, K]. The default is
  *                       the smallest of 4, 8, 16, 32 with N <= 16 K M (thin, wide tori
  *                       get more: their solution is dominated by the lowest row bins).
- * The project's autotuner chooses the launch values per (H, W, M, N); host-only.
+ *   "row_split" N1   selects, among the row-transform entries compiled for N, the one whose
+ *                    forward pass uses the split N = N1 x N2 (a library built for the
+ *                    autotuner holds one entry per candidate split, every pass alike; the
+ *                    default library holds one entry per N, GFC_E_ARG for any other N1)
+ * The project's autotuner chooses the launch values per (H, W, M, N), and the split of each
+ * row pass per row length (compiled into the default library); host-only.
  * gfc_plan_get_param also reads the fixed "low_bins_b" (Kb: backward columns l <= Kb take
- * -D_y inside the column recursion).
+ * -D_y inside the column recursion) and "row_split_fwd", "row_split_edit", "row_split_inv",
+ * "row_split_bfwd", "row_split_binv": N1 of the split of the plain forward row pass, of its
+ * other modes (edits, a given Laplacian, volume slices), and of the inverse, backward forward
+ * and backward inverse row passes.
  */
 gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value);
 gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value);

@@ -22,7 +22,8 @@ __all__ = ["GFCError", "Plan", "lib", "lib_path", "solve", "solve_backward", "GF
            "supported_length", "default_grid", "header_functions"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libgfc.so")
+# GFC_LIBRARY names another build of the library (the autotuner's candidate library)
+_LIB_PATH = os.environ.get("GFC_LIBRARY") or os.path.join(_HERE, "libgfc.so")
 _HEADER = os.path.join(os.path.dirname(_HERE), "include", "gfc.h")
 _lib = None
 _lock = threading.Lock()
@@ -195,7 +196,7 @@ def check_workspace(ws, need: int, dev, others=()):
     return ws
 
 
-PARAMS = ("row_fppw", "row_ppw", "col_c", "col_rows", "col_rows_b", "low_bins")
+PARAMS = ("row_fppw", "row_ppw", "col_c", "col_rows", "col_rows_b", "low_bins", "row_split")
 _TUNING_PATH = os.path.join(_HERE, "tuning.json")
 _tuning_db = None
 

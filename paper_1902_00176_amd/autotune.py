@@ -13,6 +13,19 @@ tuning.json, which Plan() reads. Parameters only change speed, never results:
 
     python -m paper_1902_00176_amd.autotune --size 801 1200 1620 2400 100 [--write]
     python -m paper_1902_00176_amd.autotune --workloads [--write]
+
+Row-transform splits (--splits): each row length N = N1 * N2 can be transformed with several
+splits (both factors <= 64, the fewest lanes per slot, either order), and which is fastest
+differs between the passes (holding N1 values per lane in one stage and N2 in the other
+moves register pressure between the forward and the inverse transform). The candidate
+library, built with `python paper_1902_00176_amd/build_lib.py --tune`, holds every candidate
+of every length as its own entry; this mode times the four row passes of each candidate
+(selected with the plan parameter "row_split") and records the fastest split per pass and
+length under "row_splits" in tuning.json. The default build compiles those splits.
+
+    python paper_1902_00176_amd/build_lib.py --tune
+    GFC_LIBRARY=paper_1902_00176_amd/_build_tune/libgfc_tune.so \
+        python -m paper_1902_00176_amd.autotune --splits [--lengths 2400 2048] [--write]
 """
 from __future__ import annotations
 
@@ -130,8 +143,48 @@ def tune_size(H, W, M, N, B, torch, verbose=True):
     return best, final
 
 
+# row passes among the timed stages
+ROW_PASSES = {"fwd": "fwd1", "inv": "fwd3", "bfwd": "bwd1", "binv": "bwd3"}
+
+
+def split_shape(N):
+    """A batch whose row passes take long enough to time: the 801 x 1200 workload for its
+    2400-point rows, else 256-row images of width N / 2 (their default torus is N wide) and
+    enough of them for about 2e7 spectrum bins."""
+    if N == 2400:
+        return 801, 1200, 1620, 2400, 100
+    H, W = 256, N // 2
+    B = max(1, min(256, int(2e7 // (H * (N // 2 + 1)))))
+    return H, W, 0, N, B
+
+
+def tune_splits(lengths, torch, verbose=True):
+    """{N: {pass: [N1, N2], "ms": {pass: {"N1xN2": ms}}}} for the given row lengths."""
+    sys.path.insert(0, HERE)
+    import build_lib
+    out = {}
+    for N in lengths:
+        H, W, M, NN, B = split_shape(N)
+        ms = {ps: {} for ps in ROW_PASSES}
+        for n1, n2 in build_lib.candidate_splits(N):
+            p = gfc.Plan(H, W, M, NN, params={"row_split": n1}, tuned=False).build()
+            t = time_stages(p, B, torch=torch)
+            del p
+            for ps, st in ROW_PASSES.items():
+                ms[ps][f"{n1}x{n2}"] = round(t[st], 5)
+        best = {ps: [int(x) for x in min(v, key=v.get).split("x")] for ps, v in ms.items()}
+        out[str(N)] = {**best, "ms": ms, "shape": [H, W, M, NN, B]}
+        if verbose:
+            print(json.dumps({"N": N, **best,
+                              "ms": {ps: min(v.values()) for ps, v in ms.items()}}), flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--splits", action="store_true",
+                    help="time the candidate row splits (GFC_LIBRARY = the candidate library)")
+    ap.add_argument("--lengths", type=int, nargs="*", help="row lengths for --splits (default: all)")
     ap.add_argument("--size", type=int, nargs=5, action="append", metavar=("H", "W", "M", "N", "B"))
     ap.add_argument("--workloads", action="store_true")
     ap.add_argument("--write", action="store_true", help="update tuning.json beside this file")
@@ -151,6 +204,12 @@ def main():
         best, final = tune_size(H, W, M, N, B, torch)
         db["plans"][gfc.tuning_key(H, W, M, N)] = {**best, "tuned_batch": B,
                                                    "ms": {k: round(v, 4) for k, v in final.items()}}
+    if args.splits:
+        if not os.environ.get("GFC_LIBRARY"):
+            raise SystemExit("--splits times the candidate library: set GFC_LIBRARY to "
+                             "paper_1902_00176_amd/_build_tune/libgfc_tune.so")
+        lengths = args.lengths or [n for n in range(2, 4097, 2) if gfc.supported_length(n)]
+        db.setdefault("row_splits", {}).update(tune_splits(lengths, torch))
     for path in ([db_path] if args.write else []) + ([args.out] if args.out else []):
         with open(path, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)

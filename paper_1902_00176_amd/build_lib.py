@@ -18,6 +18,9 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 GEN = os.path.join(BUILD, "gen")
 LIB = os.path.join(HERE, "libgfc.so")
+# the autotuner's library of candidate row splits (built on demand, never shipped)
+BUILD_TUNE = os.path.join(HERE, "_build_tune")
+LIB_TUNE = os.path.join(BUILD_TUNE, "libgfc_tune.so")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -53,20 +56,71 @@ def choose_factors(N: int):
     return None if best is None else (best[1], best[2])
 
 
+MAX_ROW_LENGTH = 4096  # 64 x 64: one wavefront of 64 lanes holding 64 values each
+
+
 def default_lengths():
-    """Row lengths compiled into the library: every even 2/3/5-smooth N in [16, 2048] that
-    splits into two factors <= 64, plus 2400 (the 801 x 1200 workload's torus width)."""
-    out = []
-    for n in list(range(16, 2049, 2)) + [2400]:
-        if smooth235(n) and choose_factors(n) is not None:
-            out.append(n)
-    return sorted(set(out))
+    """Row lengths compiled into the library: every even 2/3/5-smooth N in [16, 4096] that
+    splits into two factors <= 64 (so the default torus of every image up to 2047 pixels
+    wide, and 2048 on a 4096-point row, is supported)."""
+    return [n for n in range(16, MAX_ROW_LENGTH + 1, 2)
+            if smooth235(n) and choose_factors(n) is not None]
 
 
 def z_lengths():
     """Volume depths P (the torus along z) compiled into the library: every even
     2/3/5-smooth P in [4, 512] that splits into two factors <= 64."""
     return [p for p in range(4, 513, 2) if smooth235(p) and choose_factors(p) is not None]
+
+
+TUNING = os.path.join(HERE, "tuning.json")
+PASSES = ("fwd", "inv", "bfwd", "binv")
+
+
+def candidate_splits(N: int):
+    """Splits N = N1 * N2 the autotuner compares: both factors 2/3/5-smooth and <= 64, with
+    the fewest lanes per slot (the smallest power of two >= max(N1, N2)), both orders."""
+    out = []
+    for n1 in range(2, 65):
+        if N % n1:
+            continue
+        n2 = N // n1
+        if 2 <= n2 <= 64 and smooth235(n1) and smooth235(n2):
+            out.append((n1, n2))
+    if not out:
+        return []
+    g = min(_pow2ceil(max(a, b)) for a, b in out)
+    return [(a, b) for a, b in out if _pow2ceil(max(a, b)) == g]
+
+
+def tuned_splits():
+    """Per row length and pass, the split the autotuner chose (tuning.json "row_splits"),
+    {N: {pass: (N1, N2)}}; lengths or passes it does not hold take choose_factors."""
+    import json
+    try:
+        with open(os.environ.get("GFC_TUNING_DB", TUNING)) as f:
+            raw = json.load(f).get("row_splits", {})
+    except (OSError, ValueError):
+        return {}
+    out = {}
+    for n, d in raw.items():
+        N = int(n)
+        ent = {}
+        for ps in PASSES:
+            v = d.get(ps)
+            if v and len(v) == 2 and v[0] * v[1] == N and tuple(v) in candidate_splits(N):
+                ent[ps] = (int(v[0]), int(v[1]))
+        out[N] = ent
+    return out
+
+
+def pass_splits(N: int, tuned=None):
+    """The split of each row pass of length N: tuned where tuning.json holds one, else the
+    default (fewest lanes, most balanced)."""
+    tuned = tuned_splits() if tuned is None else tuned
+    d = choose_factors(N)
+    t = tuned.get(N, {})
+    return {ps: t.get(ps, d) for ps in PASSES}
 
 
 def _z_split(P: int):
@@ -87,12 +141,14 @@ RGM_BUCKET = 12  # row lengths per multi-length ragged launch
 
 def rg_buckets(lengths):
     """Groups of row lengths that share one ragged launch: lengths of one workgroup size
-    (64 threads for 64-lane slots, else 256), in order, split into near-equal groups of at
-    most RGM_BUCKET."""
+    (64 threads for 64-lane slots, else 256) and of one side of 2048, in order, split into
+    near-equal groups of at most RGM_BUCKET."""
     cls = {}
     for n in lengths:
         n1, n2 = choose_factors(n)
-        cls.setdefault(64 if _pow2ceil(max(n1, n2)) == 64 else 256, []).append(n)
+        # class: workgroup size, and rows beyond 2048 points apart (images wider than 1024
+        # pixels), so their larger LDS and registers do not lower the occupancy of the rest
+        cls.setdefault((64 if _pow2ceil(max(n1, n2)) == 64 else 256, n > 2048), []).append(n)
     out = []
     for t in sorted(cls):
         ns = sorted(cls[t])
@@ -102,22 +158,43 @@ def rg_buckets(lengths):
     return out
 
 
-def generate(lengths):
+def generate(lengths, tune=False):
+    """Translation units: one per row length (its entry with the split of each pass), the
+    multi-length ragged groups, the table of entries and the z transforms. tune=True: every
+    candidate split of every length as its own entry (plain passes only), for the autotuner."""
     os.makedirs(GEN, exist_ok=True)
     srcs = []
+    tuned = tuned_splits()
+    entries = []  # (symbol, N)
     for n in lengths:
-        n1, n2 = choose_factors(n)
         path = os.path.join(GEN, f"row_{n}.hip")
-        text = (f'#include "gfc_row.h"\n'
-                f"namespace gfc {{\n"
-                f"const RowKernels* gfc_row_entry_{n}() {{\n"
-                f"  static const RowKernels k = GFC_ROW_ENTRY({n1}, {n2});\n"
-                f"  return &k;\n}}\n}}  // namespace gfc\n")
+        body = ""
+        if tune:
+            for n1, n2 in candidate_splits(n):
+                sym = f"gfc_row_entry_{n}_{n1}"
+                body += (f"const RowKernels* {sym}() {{\n"
+                         f"  static const RowKernels k = GFC_ROW_ENTRY_CANDIDATE({n1}, {n2});\n"
+                         f"  return &k;\n}}\n")
+                entries.append((sym, n))
+        else:
+            sp = pass_splits(n, tuned)
+            # the forward modes other than the plain solve keep the default split
+            order = [sp["fwd"], choose_factors(n), sp["inv"], sp["bfwd"], sp["binv"]]
+            args = ", ".join(f"{a}, {b}" for a, b in order)
+            sym = f"gfc_row_entry_{n}"
+            body = (f"const RowKernels* {sym}() {{\n"
+                    f"  static const RowKernels k = GFC_ROW_ENTRY({args});\n"
+                    f"  return &k;\n}}\n")
+            entries.append((sym, n))
+        text = f'#include "gfc_row.h"\nnamespace gfc {{\n{body}}}  // namespace gfc\n'
         _write_if_changed(path, text)
         srcs.append(path)
-    buckets = rg_buckets(lengths)
+    buckets = [] if tune else rg_buckets(lengths)
     for k, ns in enumerate(buckets):
-        lens = ", ".join(f"RowLen<{choose_factors(n)[0]}, {choose_factors(n)[1]}>" for n in ns)
+        def rl(n):
+            sp = pass_splits(n, tuned)
+            return f"RowLen<{sp['fwd'][0]}, {sp['fwd'][1]}, {sp['inv'][0]}, {sp['inv'][1]}>"
+        lens = ", ".join(rl(n) for n in ns)
         path = os.path.join(GEN, f"row_rgm_{k}.hip")
         text = (f'#include "gfc_row.h"\n'
                 f"namespace gfc {{\n"
@@ -130,16 +207,21 @@ def generate(lengths):
     rgm_decl = "".join(f"const RgMulti* gfc_rgm_entry_{k}();\n" for k in range(len(buckets)))
     rgm_cases = "".join(f"    case {n}: return gfc_rgm_entry_{k}();\n"
                         for k, ns in enumerate(buckets) for n in ns)
-    decl = rgm_decl + "".join(f"const RowKernels* gfc_row_entry_{n}();\n" for n in lengths)
-    calls = ",\n      ".join(f"gfc_row_entry_{n}()" for n in lengths)
+    decl = rgm_decl + "".join(f"const RowKernels* {sym}();\n" for sym, _ in entries)
+    calls = ",\n      ".join(f"{sym}()" for sym, _ in entries)
+    ne = len(entries)
     table = (f'#include "gfc_internal.h"\nnamespace gfc {{\n{decl}'
              f"static const RowKernels* const* table() {{\n"
              f"  static const RowKernels* const t[] = {{\n      {calls}}};\n  return t;\n}}\n"
-             f"int row_kernel_count() {{ return {len(lengths)}; }}\n"
+             f"int row_kernel_count() {{ return {ne}; }}\n"
              f"const RowKernels* row_kernel_at(int i) {{ return table()[i]; }}\n"
              f"const RowKernels* find_row_kernels(int N) {{\n"
-             f"  for (int i = 0; i < {len(lengths)}; ++i)\n"
+             f"  for (int i = 0; i < {ne}; ++i)\n"
              f"    if (table()[i]->N == N) return table()[i];\n"
+             f"  return nullptr;\n}}\n"
+             f"const RowKernels* find_row_kernels_split(int N, int N1) {{\n"
+             f"  for (int i = 0; i < {ne}; ++i)\n"
+             f"    if (table()[i]->N == N && table()[i]->f.N1 == N1) return table()[i];\n"
              f"  return nullptr;\n}}\n"
              f"const RgMulti* find_rg_multi(int N) {{\n  switch (N) {{\n{rgm_cases}"
              f"    default: return nullptr;\n  }}\n}}\n}}  // namespace gfc\n")
@@ -175,14 +257,20 @@ def _compile(src, obj):
     return obj
 
 
-def build(lengths=None, jobs=None, verbose=True, force=False):
+def build(lengths=None, jobs=None, verbose=True, force=False, tune=False):
+    """Compile the library. tune=True builds the autotuner's candidate library instead:
+    every candidate split of every row length, plain passes only, written to LIB_TUNE in a
+    build folder of its own (the default library is not touched)."""
+    global BUILD, GEN, LIB
+    if tune:
+        BUILD, GEN, LIB = BUILD_TUNE, os.path.join(BUILD_TUNE, "gen"), LIB_TUNE
     lengths = lengths or _lengths_from_env()
     if os.path.isdir(BUILD) and force:
         shutil.rmtree(BUILD)
     os.makedirs(BUILD, exist_ok=True)
     units = ("gfc_api.hip", "gfc_col.hip", "gfc_ragged.hip", "gfc_color.hip", "gfc_lowext.hip",
              "gfc_noalloc.hip")
-    srcs = [os.path.join(CSRC, f) for f in units] + generate(lengths)
+    srcs = [os.path.join(CSRC, f) for f in units] + generate(lengths, tune=tune)
     headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     headers.append(os.path.join(INCLUDE, "gfc.h"))
     newest_hdr = max(os.path.getmtime(h) for h in headers)
@@ -213,4 +301,4 @@ def build(lengths=None, jobs=None, verbose=True, force=False):
 
 
 if __name__ == "__main__":
-    build(force="--force" in sys.argv)
+    build(force="--force" in sys.argv, tune="--tune" in sys.argv)

@@ -144,7 +144,7 @@ void derive_geometry(gfc_plan_s* p) {
   p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
   p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
   const int slots_needed = (p->npairs + p->row_ppw - 1) / p->row_ppw;
-  p->nsums = (slots_needed + p->rk->slots - 1) / p->rk->slots;
+  p->nsums = (slots_needed + p->rk->bf.slots - 1) / p->rk->bf.slots;
 }
 
 }  // namespace
@@ -239,6 +239,10 @@ gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
   } else if (!std::strcmp(name, "low_bins")) {
     if (value < kLowBins || value > kMaxLowBins || 2 * value >= p->N) return GFC_E_ARG;
     p->K = value;
+  } else if (!std::strcmp(name, "row_split")) {
+    const RowKernels* rk = find_row_kernels_split(p->N, value);
+    if (!rk) return GFC_E_ARG;
+    p->rk = rk;
   } else {
     return GFC_E_ARG;
   }
@@ -255,6 +259,12 @@ gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
   else if (!std::strcmp(name, "col_rows_b")) *value = p->col_rows_b;
   else if (!std::strcmp(name, "low_bins")) *value = p->K;
   else if (!std::strcmp(name, "low_bins_b")) *value = p->Kb;
+  else if (!std::strcmp(name, "row_split")) *value = p->rk->f.N1;
+  else if (!std::strcmp(name, "row_split_fwd")) *value = p->rk->f.N1;
+  else if (!std::strcmp(name, "row_split_edit")) *value = p->rk->e.N1;
+  else if (!std::strcmp(name, "row_split_inv")) *value = p->rk->i.N1;
+  else if (!std::strcmp(name, "row_split_bfwd")) *value = p->rk->bf.N1;
+  else if (!std::strcmp(name, "row_split_binv")) *value = p->rk->bi.N1;
   else return GFC_E_ARG;
   return GFC_OK;
 }
@@ -262,26 +272,54 @@ gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
 gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   if (!p) return GFC_E_ARG;
   if (p->built) return GFC_OK;
-  const int N = p->N, N1 = p->rk->N1, N2 = p->rk->N2, NH = p->NH;
-  // four-step twiddles w_N^(k1 j): [N1][N2] for the forward step, [N2][N1] for the inverse
-  std::vector<f2> twA(size_t(N1) * N2), twB(size_t(N1) * N2), sxm(NH), dsh(NH);
-  // low-bin twiddles of the forward row pass, lane j < N2 of a G-lane slot:
+  const int N = p->N, NH = p->NH;
+  // four-step twiddles w_N^(k1 j) of each pass's split N = N1 N2: [N1][N2] for a forward
+  // transform (forward and backward-forward row passes), [N2][N1] for an inverse one
+  auto tw_fwd = [&](const RowSplit& q) {
+    std::vector<f2> t(size_t(q.N1) * q.N2);
+    for (int k1 = 0; k1 < q.N1; ++k1)
+      for (int j = 0; j < q.N2; ++j) {
+        double c, s;
+        cs2pi(long(k1) * j, N, c, s);
+        t[size_t(k1) * q.N2 + j] = f2{float(c), float(-s)};
+      }
+    return t;
+  };
+  auto tw_inv = [&](const RowSplit& q) {
+    std::vector<f2> t(size_t(q.N1) * q.N2);
+    for (int k1 = 0; k1 < q.N1; ++k1)
+      for (int j = 0; j < q.N2; ++j) {
+        double c, s;
+        cs2pi(long(k1) * j, N, c, s);
+        t[size_t(j) * q.N1 + k1] = f2{float(c), float(-s)};
+      }
+    return t;
+  };
+  const std::vector<f2> twA = tw_fwd(p->rk->f), twAe = tw_fwd(p->rk->e);
+  const std::vector<f2> twB = tw_inv(p->rk->i);
+  const std::vector<f2> twAb = tw_fwd(p->rk->bf), twBb = tw_inv(p->rk->bi);
+  std::vector<f2> sxm(NH), dsh(NH);
+  // low-bin twiddles of a forward row pass, lane j < N2 of a G-lane slot:
   // [0][l][j] = (1 - w_N^l) w_N^(l j) for Ex, [1][l][j] = w_N^(l j) for Ey (0 for j >= N2)
-  const int G = p->rk->G, K1 = kLowBins + 1;
-  std::vector<f2> twL(size_t(2) * K1 * G, f2{0.f, 0.f});
-  for (int l = 0; l < K1; ++l) {
-    const double h = std::sin(kPi * double(l) / double(N));
-    double c, s;
-    cs2pi(l, N, c, s);
-    const double ar = 2.0 * h * h, ai = s;  // 1 - e^{-i 2 pi l / N}
-    for (int j = 0; j < N2; ++j) {
-      double cj, sj;
-      cs2pi(long(l) * j, N, cj, sj);
-      const double wr = cj, wi = -sj;  // e^{-i 2 pi l j / N}
-      twL[size_t(l) * G + j] = f2{float(ar * wr - ai * wi), float(ar * wi + ai * wr)};
-      twL[size_t(K1 + l) * G + j] = f2{float(wr), float(wi)};
+  const int K1 = kLowBins + 1;
+  auto tw_low = [&](const RowSplit& q) {
+    std::vector<f2> t(size_t(2) * K1 * q.G, f2{0.f, 0.f});
+    for (int l = 0; l < K1; ++l) {
+      const double h = std::sin(kPi * double(l) / double(N));
+      double c, s;
+      cs2pi(l, N, c, s);
+      const double ar = 2.0 * h * h, ai = s;  // 1 - e^{-i 2 pi l / N}
+      for (int j = 0; j < q.N2; ++j) {
+        double cj, sj;
+        cs2pi(long(l) * j, N, cj, sj);
+        const double wr = cj, wi = -sj;  // e^{-i 2 pi l j / N}
+        t[size_t(l) * q.G + j] = f2{float(ar * wr - ai * wi), float(ar * wi + ai * wr)};
+        t[size_t(K1 + l) * q.G + j] = f2{float(wr), float(wi)};
+      }
     }
-  }
+    return t;
+  };
+  const std::vector<f2> twL = tw_low(p->rk->f), twLe = tw_low(p->rk->e);
   // direct-sum twiddles of the extra split bins: w_N^m for m < N, then 1 - w_N^l
   std::vector<f2> twX(size_t(N) + kMaxLowBins + 1);
   for (int m = 0; m < N; ++m) {
@@ -295,13 +333,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
     cs2pi(l, N, c, s);
     twX[size_t(N) + l] = f2{float(2.0 * h * h), float(s)};
   }
-  for (int k1 = 0; k1 < N1; ++k1)
-    for (int j = 0; j < N2; ++j) {
-      double c, s;
-      cs2pi(long(k1) * j, N, c, s);
-      twA[size_t(k1) * N2 + j] = f2{float(c), float(-s)};
-      twB[size_t(j) * N1 + k1] = f2{float(c), float(-s)};
-    }
   for (int l = 0; l < NH; ++l) {
     double c, s;
     cs2pi(l, N, c, s);
@@ -326,7 +357,11 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   size_t off = 0;
   const size_t o_twA = off; off = align256(off + twA.size() * sizeof(f2));
   const size_t o_twB = off; off = align256(off + twB.size() * sizeof(f2));
+  const size_t o_twAb = off; off = align256(off + twAb.size() * sizeof(f2));
+  const size_t o_twBb = off; off = align256(off + twBb.size() * sizeof(f2));
   const size_t o_twL = off; off = align256(off + twL.size() * sizeof(f2));
+  const size_t o_twAe = off; off = align256(off + twAe.size() * sizeof(f2));
+  const size_t o_twLe = off; off = align256(off + twLe.size() * sizeof(f2));
   const size_t o_twX = off; off = align256(off + twX.size() * sizeof(f2));
   const size_t o_sxm = off; off = align256(off + sxm.size() * sizeof(f2));
   const size_t o_dsh = off; off = align256(off + dsh.size() * sizeof(f2));
@@ -336,7 +371,11 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   std::vector<unsigned char> host(off, 0);
   std::memcpy(host.data() + o_twA, twA.data(), twA.size() * sizeof(f2));
   std::memcpy(host.data() + o_twB, twB.data(), twB.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twAb, twAb.data(), twAb.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twBb, twBb.data(), twBb.size() * sizeof(f2));
   std::memcpy(host.data() + o_twL, twL.data(), twL.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twAe, twAe.data(), twAe.size() * sizeof(f2));
+  std::memcpy(host.data() + o_twLe, twLe.data(), twLe.size() * sizeof(f2));
   std::memcpy(host.data() + o_twX, twX.data(), twX.size() * sizeof(f2));
   std::memcpy(host.data() + o_sxm, sxm.data(), sxm.size() * sizeof(f2));
   std::memcpy(host.data() + o_dsh, dsh.data(), dsh.size() * sizeof(f2));
@@ -356,7 +395,11 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   p->dmem = d;
   p->twA = reinterpret_cast<f2*>(base + o_twA);
   p->twB = reinterpret_cast<f2*>(base + o_twB);
+  p->twAb = reinterpret_cast<f2*>(base + o_twAb);
+  p->twBb = reinterpret_cast<f2*>(base + o_twBb);
   p->twL = reinterpret_cast<f2*>(base + o_twL);
+  p->twAe = reinterpret_cast<f2*>(base + o_twAe);
+  p->twLe = reinterpret_cast<f2*>(base + o_twLe);
   p->twX = reinterpret_cast<f2*>(base + o_twX);
   p->sxm = reinterpret_cast<f2*>(base + o_sxm);
   p->dshift = reinterpret_cast<f2*>(base + o_dsh);
@@ -441,6 +484,10 @@ static gfc_status solve_forward(gfc_plan_t p, const float* gx, const float* gy, 
   f.C = C;
   f.tau2 = tau2;
   f.alpha = alpha;
+  if (edit != kEditNone) {  // the edited and Laplacian forward modes use their own split
+    f.twA = p->twAe;
+    f.twL = p->twLe;
+  }
   gfc_status st = hip_status(p->rk->fwd(f, B, s));
   if (st != GFC_OK) return st;
   if (edit != kInLaplacian) {
@@ -545,7 +592,7 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     a.du = du;
     a.U = T;
     a.sums = sums;
-    a.twA = p->twA;
+    a.twA = p->twAb;
     a.H = p->H;
     a.W = p->W;
     a.npairs = (p->H + 1) / 2;
@@ -587,7 +634,7 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     v.SD = SD;
     v.dgx = dgx;
     v.dgy = dgy;
-    v.twB = p->twB;
+    v.twB = p->twBb;
     v.sxm = p->sxm;
     v.H = p->H;
     v.W = p->W;
@@ -795,6 +842,8 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   //    l <= K split: T gets (1 - w_N^l) Ex^, SB gets Ey^ and SZ gets Ez^ of planes z < D
   RowFwdArgs f = row_fwd_args(p, gx, gy, T, SB);
   f.edit = kIn3D;
+  f.twA = p->twAe;  // volume slices: the forward split of the non-plain modes
+  f.twL = p->twLe;
   f.gz = gz;
   f.zd = D;
   f.zp = P;

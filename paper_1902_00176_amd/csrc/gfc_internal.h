@@ -237,8 +237,16 @@ hipError_t launch_sz_combine(f2* T, const f2* SZ, const f2* omz, int H, int NHP,
                              int P, long long plane_t, long long plane_s, int B, hipStream_t s);
 
 // launchers (defined in the kernel files)
+// The split N = N1 * N2 of one row pass's four-step FFT: lane slots of G lanes, `slots` of
+// them per workgroup. Each pass of a row length has its own (chosen by the autotuner).
+struct RowSplit {
+  int N1, N2, G, slots;
+};
 struct RowKernels {
-  int N, N1, N2, G, slots;
+  int N;
+  // plain forward, other forward modes (edits, Laplacian input, volume slices), inverse,
+  // backward forward and backward inverse row passes
+  RowSplit f, e, i, bf, bi;
   hipError_t (*fwd)(const RowFwdArgs&, int B, hipStream_t);
   hipError_t (*inv)(const RowInvArgs&, int B, hipStream_t);
   hipError_t (*bfwd)(const RowBwdFwdArgs&, int B, hipStream_t);
@@ -248,6 +256,9 @@ struct RowKernels {
   hipError_t (*rg_inv)(const RgBase*, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
 };
 const RowKernels* find_row_kernels(int N);
+// the entry for N whose forward row pass uses N1 (a library built for split tuning holds one
+// entry per candidate split; the default library one per length)
+const RowKernels* find_row_kernels_split(int N, int N1);
 // ragged launches that cover several row lengths of one workgroup size (half support only)
 struct RgMulti {
   int id;  // distinct per group of lengths

@@ -40,8 +40,11 @@ struct gfc_plan_s {
   bool built = false;
   int device = -1;
   void* dmem = nullptr;
-  gfc::f2 *twA = nullptr, *twB = nullptr, *twL = nullptr, *twX = nullptr, *sxm = nullptr,
-          *dshift = nullptr;
+  // four-step twiddles of each row pass's split: twA plain forward, twAe the other forward
+  // modes, twB inverse, twAb backward forward, twBb backward inverse; twL / twLe the low-bin
+  // lane factors of the two forward splits
+  gfc::f2 *twA = nullptr, *twAe = nullptr, *twB = nullptr, *twAb = nullptr, *twBb = nullptr,
+          *twL = nullptr, *twLe = nullptr, *twX = nullptr, *sxm = nullptr, *dshift = nullptr;
   double* twD = nullptr;  // [N][2] float64 w_N^m (direct sums of a given Laplacian's low bins)
   gfc::ColConst *ccf = nullptr, *ccb = nullptr;
   // a side stream for the forward column pass's low tiles, joined back with two events
@@ -57,7 +60,7 @@ namespace gfc {
 // workgroups of the inverse row pass (one moment pair each for the colour correction)
 inline int inv_groups(const gfc_plan_s* p) {
   const int slots_needed = ((p->H + 1) / 2 + p->row_ppw - 1) / p->row_ppw;
-  return (slots_needed + p->rk->slots - 1) / p->rk->slots;
+  return (slots_needed + p->rk->i.slots - 1) / p->rk->i.slots;
 }
 
 // workspace of a batch: spectra T, side arrays (SB forward / SD backward), reductions,

@@ -316,7 +316,7 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
     for (int i : ch) {
       g.half = g.half && 2 * r->W[i] <= r->N[i];
       const gfc_plan_s* p = r->plans[r->plan_of[i]];
-      const int slots = p->rk->slots;
+      const int slots = p->rk->f.slots;
       const int nb = (p->nfslots + slots - 1) / slots;
       for (int k = 0; k < nb; ++k) items.push_back(RgItem{i, k});
     }
@@ -324,7 +324,7 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
     g.i_off = int(items.size());
     for (int i : ch) {
       const gfc_plan_s* p = r->plans[r->plan_of[i]];
-      const int slots = p->rk->slots;
+      const int slots = p->rk->i.slots;
       const int need = (p->npairs + p->row_ppw - 1) / p->row_ppw;
       const int nb = (need + slots - 1) / slots;
       for (int k = 0; k < nb; ++k) items.push_back(RgItem{i, k});

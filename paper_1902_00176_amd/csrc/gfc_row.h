@@ -1015,7 +1015,9 @@ k_row_binv(RowBwdInvArgs p) {
 // ---------------------------------------------------------------------------------------
 // launchers
 
-template <int N1, int N2>
+// ALL = false: the forward launcher handles the plain solve only (the candidate entries of a
+// library built for split tuning, which times the plain passes)
+template <int N1, int N2, bool ALL = true>
 struct RowLaunch {
   using C = RowCfg<N1, N2>;
   // 64-lane slots run one wavefront per workgroup; narrower slots fill 256-thread groups
@@ -1028,6 +1030,12 @@ struct RowLaunch {
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
     const bool half = 2 * a.W <= N1 * N2;
     const dim3 blk(SLOTS * C::G);
+    if constexpr (!ALL) {
+      if (a.edit != kEditNone) return hipErrorInvalidValue;
+      if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditNone>), grid, blk, 0, s, a);
+      return hipGetLastError();
+    }
     switch (a.edit) {
       case kEditThreshold:
         if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditThreshold>), grid, blk, 0, s, a);
@@ -1098,14 +1106,18 @@ struct RowLaunch {
 // cuts the launches per row pass to a handful. The LDS is the largest of the lengths'; the
 // registers are the most any of them needs. Only the half-support forward variant (2 W <= N,
 // every default torus) is grouped.
-template <int N1_, int N2_>
+template <int F1, int F2, int I1, int I2>
 struct RowLen {
-  static constexpr int N1 = N1_, N2 = N2_, N = N1_ * N2_;
-  static constexpr int SLOTS = RowLaunch<N1_, N2_>::SLOTS;
-  static constexpr int NBH = RowLaunch<N1_, N2_>::NB_HALF;
-  static constexpr int THREADS = SLOTS * RowCfg<N1_, N2_>::G;
-  static constexpr int FWD_LDS = kFwdLds<N1_, N2_, SLOTS>;
-  static constexpr int INV_LDS = kInvLds<N1_, N2_, SLOTS>;
+  // forward row pass with the split F1 x F2, inverse with I1 x I2 (N = F1 F2 = I1 I2)
+  static constexpr int N = F1 * F2;
+  static_assert(I1 * I2 == N, "one row length per entry");
+  static constexpr int FSLOTS = RowLaunch<F1, F2>::SLOTS, ISLOTS = RowLaunch<I1, I2>::SLOTS;
+  static constexpr int NBH = RowLaunch<F1, F2>::NB_HALF;
+  static constexpr int THREADS = FSLOTS * RowCfg<F1, F2>::G;
+  static_assert(ISLOTS * RowCfg<I1, I2>::G == THREADS, "one workgroup size per entry");
+  static constexpr int FWD_LDS = kFwdLds<F1, F2, FSLOTS>;
+  static constexpr int INV_LDS = kInvLds<I1, I2, ISLOTS>;
+  static constexpr int FN1 = F1, FN2 = F2, IN1 = I1, IN2 = I2;
 };
 constexpr int cmax_n(int a) { return a; }
 template <class... T>
@@ -1126,10 +1138,10 @@ k_row_fwd_rgm(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
   p.T1 = reinterpret_cast<f2*>(base.ws + e.t);
   p.SB = reinterpret_cast<f2*>(base.ws + e.side);
   const int n = p.N;
-  (void)((n == L0::N && (row_fwd_body<L0::N1, L0::N2, L0::SLOTS, L0::NBH>(p, it.blk, 0, lds),
+  (void)((n == L0::N && (row_fwd_body<L0::FN1, L0::FN2, L0::FSLOTS, L0::NBH>(p, it.blk, 0, lds),
                          true)) ||
          ... ||
-         (n == Ls::N && (row_fwd_body<Ls::N1, Ls::N2, Ls::SLOTS, Ls::NBH>(p, it.blk, 0, lds),
+         (n == Ls::N && (row_fwd_body<Ls::FN1, Ls::FN2, Ls::FSLOTS, Ls::NBH>(p, it.blk, 0, lds),
                          true)));
 }
 
@@ -1146,9 +1158,9 @@ k_row_inv_rgm(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
   p.u = base.u + e.out;
   p.partial = reinterpret_cast<const double*>(base.ws + e.red);
   const int n = p.N;
-  (void)((n == L0::N && (row_inv_body<L0::N1, L0::N2, L0::SLOTS>(p, it.blk, 0, lds), true)) ||
+  (void)((n == L0::N && (row_inv_body<L0::IN1, L0::IN2, L0::ISLOTS>(p, it.blk, 0, lds), true)) ||
          ... ||
-         (n == Ls::N && (row_inv_body<Ls::N1, Ls::N2, Ls::SLOTS>(p, it.blk, 0, lds), true)));
+         (n == Ls::N && (row_inv_body<Ls::IN1, Ls::IN2, Ls::ISLOTS>(p, it.blk, 0, lds), true)));
 }
 
 template <class L0, class... Ls>
@@ -1167,9 +1179,35 @@ struct RowMulti {
   }
 };
 
-#define GFC_ROW_ENTRY(n1, n2)                                                               \
-  RowKernels{n1 * n2, n1, n2, RowCfg<n1, n2>::G, RowLaunch<n1, n2>::SLOTS,                   \
-             &RowLaunch<n1, n2>::fwd, &RowLaunch<n1, n2>::inv, &RowLaunch<n1, n2>::bfwd,     \
-             &RowLaunch<n1, n2>::binv, &RowLaunch<n1, n2>::rg_fwd, &RowLaunch<n1, n2>::rg_inv}
+template <int N1, int N2>
+constexpr RowSplit row_split() {
+  return RowSplit{N1, N2, RowCfg<N1, N2>::G, RowLaunch<N1, N2>::SLOTS};
+}
+
+// The forward row pass: the plain solve with the split F1 x F2, the other input modes
+// (gradient edits, a given Laplacian, volume slices) with E1 x E2 (each mode's fastest split
+// differs: its loader holds other values through the first FFT stage).
+template <int F1, int F2, int E1, int E2>
+struct RowFwdModes {
+  static hipError_t fwd(const RowFwdArgs& a, int B, hipStream_t s) {
+    if (a.edit == kEditNone) return RowLaunch<F1, F2, false>::fwd(a, B, s);
+    return RowLaunch<E1, E2>::fwd(a, B, s);
+  }
+};
+
+// One row length with its own split per pass: plain forward (f1 x f2), the other forward
+// modes (e1 x e2), inverse (i1 x i2), backward forward (b1 x b2) and backward inverse
+// (c1 x c2) row transforms.
+#define GFC_ROW_ENTRY(f1, f2, e1, e2, i1, i2, b1, b2, c1, c2)                                \
+  RowKernels{f1 * f2, row_split<f1, f2>(), row_split<e1, e2>(), row_split<i1, i2>(),        \
+             row_split<b1, b2>(), row_split<c1, c2>(), &RowFwdModes<f1, f2, e1, e2>::fwd,    \
+             &RowLaunch<i1, i2>::inv, &RowLaunch<b1, b2>::bfwd, &RowLaunch<c1, c2>::binv,    \
+             &RowLaunch<f1, f2>::rg_fwd, &RowLaunch<i1, i2>::rg_inv}
+// A candidate split for the autotuner: every pass with n1 x n2, the plain passes only.
+#define GFC_ROW_ENTRY_CANDIDATE(n1, n2)                                                       \
+  RowKernels{n1 * n2, row_split<n1, n2>(), row_split<n1, n2>(), row_split<n1, n2>(),        \
+             row_split<n1, n2>(), row_split<n1, n2>(), &RowLaunch<n1, n2, false>::fwd,      \
+             &RowLaunch<n1, n2, false>::inv, &RowLaunch<n1, n2, false>::bfwd,               \
+             &RowLaunch<n1, n2, false>::binv, nullptr, nullptr}
 
 }  // namespace gfc

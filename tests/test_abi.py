@@ -34,7 +34,9 @@ def test_status_strings():
     (10, 10, 12, 24, 0), (801, 1200, 0, 0, 0), (64, 64, 128, 128, 0),
     (1, 1, 0, 0, 0), (4, 4, 0, 0, 0), (32767, 4, 0, 0, 0),  # tiny and tallest default tori
     (1 << 15, 4, 0, 0, 2), (4, (1 << 15) + 1, 0, 0, 2),    # past the height / width limits
-    (10, 1300, 0, 0, 2),   # default N = 2600 has no row FFT
+    (10, 1300, 0, 0, 0), (10, 1100, 0, 0, 0), (10, 1920, 0, 0, 0),  # default N 2700, 2250, 3840
+    (10, 2047, 0, 0, 0),   # the widest default torus: N = 4096
+    (10, 2049, 0, 0, 2),   # default N = 4320 has no row FFT (longest: 4096)
     (10, 2399, 0, 2400, 2),  # N < W + 2
 ])
 def test_plan_create_validation(H, W, M, N, status):
@@ -85,9 +87,10 @@ def test_exported_green_spectrum_matches_oracle(H, W, M, N):
 
 
 def test_supported_lengths_cover_the_workloads():
-    for n in (64, 128, 512, 1024, 2048, 2400, 1620, 1200):
+    for n in (64, 128, 512, 1024, 2048, 2400, 1620, 1200, 2250, 2560, 3840, 4096):
         assert gfc.supported_length(n), n
-    assert not gfc.supported_length(22)
+    for n in (22, 4100, 4320, 4608):
+        assert not gfc.supported_length(n), n
 
 
 def test_ragged_create_host_logic():
@@ -124,8 +127,19 @@ def test_plan_parameters_round_trip_and_low_bins():
     want = {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32, "col_rows_b": 16,
             "low_bins": 4}
     p = gfc.Plan(801, 1200, params=want, tuned=False)
-    assert p.params == want
+    got = p.params
+    assert got.pop("row_split") == p.get_param("row_split_fwd")
+    assert got == want
     assert p.get_param("low_bins_b") == 64
+    # the split of each row pass is one compiled for the length; others are refused
+    import sys
+    sys.path.insert(0, os.path.dirname(gfc.__file__))
+    import build_lib
+    cands = build_lib.candidate_splits(2400)
+    for ps in ("fwd", "edit", "inv", "bfwd", "binv"):
+        n1 = p.get_param("row_split_" + ps)
+        assert (n1, 2400 // n1) in cands, (ps, n1)
+    assert gfc.lib().gfc_plan_set_param(p.handle, b"row_split", 7) == 1
     L = gfc.lib()
     for name, value in (("row_fppw", 0), ("row_fppw", 65), ("col_c", 3), ("col_rows", 24),
                         ("col_rows_b", 8), ("low_bins", 3), ("low_bins", 33),

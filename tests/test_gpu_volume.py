@@ -61,12 +61,13 @@ SHAPES = [  # D, H, W, P, M, N: default tori, an odd size, minimal padding, a de
 
 def test_volume_plan_limits():
     """The z transform is compiled for depths P <= 512 and the rows for the supported row
-    lengths (up to 2400); other sizes are refused."""
+    lengths (up to 4096); other sizes are refused."""
     with pytest.raises(gfc.GFCError):
         gfc.Plan3(300, 8, 8)     # default P = 600
     with pytest.raises(gfc.GFCError):
-        gfc.Plan3(4, 8, 1300)    # default N = 2600 has no row FFT
+        gfc.Plan3(4, 8, 2100)    # default N = 4320 has no row FFT
     gfc.Plan3(4, 8, 1200)        # N = 2400 is accepted
+    gfc.Plan3(4, 8, 1300)        # N = 2700 is accepted
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])) + f"@{s[3] or 'd'}")
