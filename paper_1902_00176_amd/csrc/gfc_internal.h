@@ -253,7 +253,8 @@ struct RowKernels {
   hipError_t (*binv)(const RowBwdInvArgs&, int B, hipStream_t);
   hipError_t (*rg_fwd)(const RgBase*, const RgRowFwd*, const RgItem*, int nitems, bool half,
                        hipStream_t);
-  hipError_t (*rg_inv)(const RgBase*, const RgRowInv*, const RgItem*, int nitems, hipStream_t);
+  hipError_t (*rg_inv)(const RgBase*, const RgRowInv*, const RgItem*, int nitems, bool half,
+                       hipStream_t);
 };
 const RowKernels* find_row_kernels(int N);
 // the entry for N whose forward row pass uses N1 (a library built for split tuning holds one

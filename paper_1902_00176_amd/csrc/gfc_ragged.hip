@@ -153,7 +153,8 @@ gfc_status enqueue(gfc_ragged_s* r, const RgBase* base, hipStream_t main) {
       const auto& G = r->groups[g];
       if (G.i_n == 0) continue;
       const hipError_t e = G.mk ? G.mk->inv(base, r->tab_i, r->items + G.i_off, G.i_n, st[k])
-                                : G.rk->rg_inv(base, r->tab_i, r->items + G.i_off, G.i_n, st[k]);
+                                : G.rk->rg_inv(base, r->tab_i, r->items + G.i_off, G.i_n,
+                                               G.half, st[k]);
       if (e != hipSuccess) return GFC_E_HIP;
     }
   }

@@ -665,6 +665,33 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     // Z = FFT(L[y0] + i L[y0+1]): L^[y0, l] = (Z[l] + conj Z[N-l]) / 2,
     // L^[y0+1, l] = (Z[l] - conj Z[N-l]) / 2i; bins l <= K come from the direct sums
     const bool has1 = ok && y0 + 1 <= p.H;
+    if constexpr (SLOTS == 1) {
+      // uniform rows: a descriptor per T1 row with range NH bins (empty outside the image),
+      // so bins l >= NH and missing rows are dropped by the hardware with no branch
+      const f2* t1b = p.T1 + tplane * p.img_t1;
+      const rsrc_t w0 = make_buf(t1b + (long long)y0 * C::NHP, ok ? C::NH * 8 : 0);
+      const rsrc_t w1 = make_buf(t1b + (long long)(y0 + 1) * C::NHP, has1 ? C::NH * 8 : 0);
+#pragma unroll
+      for (int i = 0; i < C::NI; ++i) {
+        const int l = lane + C::G * i;
+        // mirror bin N - l (0 for l = 0, and for lanes past NH whose stores are dropped)
+        const bool inside = C::G * i + C::G - 1 < C::NH ? true : l < C::NH;
+        const int m = (i == 0 && lane == 0) || !inside ? 0 : C::N - l;
+        const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
+        cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
+        cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
+        int off = (lane + C::G * i) * 8 + tz;
+        if constexpr (!FULLBINS) {
+          if (i == 0) {
+            // bins 1..K come from the direct sums; bin 0 of T1 is (1 - w_N^0) Ex^ = 0
+            if (lane == 0) A = B = {0.f, 0.f};
+            else if (lane <= KL) off = kOOB;
+          }
+        }
+        bst2(w0, A.x, A.y, off, 0);
+        bst2(w1, B.x, B.y, off, 0);
+      }
+    } else {
 #pragma unroll
     for (int i = 0; i < C::NI; ++i) {
       const int l = lane + C::G * i;
@@ -688,6 +715,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
         if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
       }
+    }
     }
 #pragma unroll
     for (int k = 0; k < NVL; ++k) {
@@ -750,13 +778,18 @@ k_row_fwd_rg(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
 // MOM: also the float64 sums of the stored values and their squares, one pair per
 // workgroup (fixed summation order), for the colour correction of eq. (25).
 // lds: kInvLds<N1, N2, SLOTS> floats of the workgroup's LDS
-template <int N1, int N2, int SLOTS, bool MOM = false>
+// Output blocks j1 of the inverse row pass that can hold x = lane + N2 j1 < W when 2 W <= N
+template <int N1>
+constexpr int kInvHalf = (N1 + 1) / 2;
+
+// NBO: output blocks j1 that can hold x < W (N1, or kInvHalf<N1> when 2 W <= N)
+template <int N1, int N2, int SLOTS, bool MOM = false, int NBO = N1>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, float* lds) {
   using C = RowCfg<N1, N2>;
   __shared__ double s_mom[SLOTS][2];
   double m1 = 0.0, m2 = 0.0;
-  const int slot = threadIdx.x / C::G;
-  const int lane = threadIdx.x % C::G;
+  const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
+  const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
   float* re = lds + slot * C::LDSC;
   float* im = lds + (SLOTS + slot) * C::LDSC;
   // image b, or slice z = b % zd of volume b / zd (its spectra are plane z of zp)
@@ -779,6 +812,40 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
     const bool ok = q < p.npairs;
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
+    if constexpr (SLOTS == 1 && !MOM) {
+      // One slot per wavefront: the rows are uniform, and each output row gets a descriptor
+      // whose range is that row (empty outside the image): stores at x >= W are dropped by
+      // the hardware, so no element needs a branch; blocks j1 >= NBO hold no x < W and are
+      // not stored at all.
+      // (the spectrum loads keep their uniform branches on the row pair: without them the
+      // compiler issued the loads two at a time, each pair followed by a full wait)
+      cx bz[N2];
+      if (lane < N1) {
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const int kk = lane + N1 * k2;
+          const int m = kk < C::NH ? kk : C::N - kk;
+          f2b X1 = {0.f, 0.f}, X2 = {0.f, 0.f};
+          if (ok) X1 = bld2(rT2, (y1 * C::NHP + m) * 8, 0);
+          if (has2) X2 = bld2(rT2, (y2 * C::NHP + m) * 8, 0);
+          if (kk < C::NH) bz[k2] = {X1.x - X2.y, X1.y + X2.x};
+          else bz[k2] = {X1.x + X2.y, X2.x - X1.y};
+        }
+      }
+      cx a[N1];
+      inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
+      const float* ub = p.u + b * p.img_u;
+      const rsrc_t u1 = make_buf(ub + (long long)y1 * p.W, ok ? (long long)p.W * 4 : 0);
+      const rsrc_t u2 = make_buf(ub + (long long)y2 * p.W, has2 ? (long long)p.W * 4 : 0);
+      const int vb = (lane < N2 ? lane * 4 : kOOB) + tz;
+#pragma unroll
+      for (int j1 = 0; j1 < NBO; ++j1) {
+        bst1(u1, a[j1].x - vref, vb + N2 * j1 * 4, 0);
+        bst1(u2, a[j1].y - vref, vb + N2 * j1 * 4, 0);
+      }
+      slot_sync();
+      continue;
+    }
     cx bz[N2];
     if (lane < N1) {
 #pragma unroll
@@ -837,14 +904,14 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
   }
 }
 
-template <int N1, int N2, int SLOTS, bool MOM>
+template <int N1, int N2, int SLOTS, bool MOM, int NBO = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_inv(RowInvArgs p) {
   __shared__ float lds[kInvLds<N1, N2, SLOTS>];
-  row_inv_body<N1, N2, SLOTS, MOM>(p, blockIdx.x, blockIdx.y, lds);
+  row_inv_body<N1, N2, SLOTS, MOM, NBO>(p, blockIdx.x, blockIdx.y, lds);
 }
 
-template <int N1, int N2, int SLOTS>
+template <int N1, int N2, int SLOTS, int NBO = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_inv_rg(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
   const RgBase base = *basep;  // written by launch_set_base on this stream
@@ -855,20 +922,21 @@ k_row_inv_rg(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
   p.u = base.u + e.out;
   p.partial = reinterpret_cast<const double*>(base.ws + e.red);
   __shared__ float lds[kInvLds<N1, N2, SLOTS>];
-  row_inv_body<N1, N2, SLOTS>(p, it.blk, 0, lds);
+  row_inv_body<N1, N2, SLOTS, false, NBO>(p, it.blk, 0, lds);
 }
 
 // ---------------------------------------------------------------------------------------
 // Backward row pass 1: row R2C of du (two rows per complex FFT) and partial sums of du.
-template <int N1, int N2, int SLOTS>
+// NB: input blocks j1 that can hold x < W (N1, or kInvHalf<N1> when 2 W <= N)
+template <int N1, int N2, int SLOTS, int NB = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_bfwd(RowBwdFwdArgs p) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
   __shared__ double s_sum[SLOTS];
-  const int slot = threadIdx.x / C::G;
-  const int lane = threadIdx.x % C::G;
+  const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
+  const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
   float* re = s_re[slot];
   float* im = s_im[slot];
   const int b = blockIdx.y;
@@ -884,7 +952,18 @@ k_row_bfwd(RowBwdFwdArgs p) {
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
     cx a[N1];
-    if (lane < N2) {
+    if constexpr (SLOTS == 1) {
+      // uniform rows: a descriptor per row whose range is that row (empty outside the
+      // image), so x >= W and missing rows read 0 with no branch; blocks j1 >= NB are 0
+      const float* db = p.du + b * p.img_in;
+      const rsrc_t d1 = make_buf(db + (long long)y1 * p.W, ok ? (long long)p.W * 4 : 0);
+      const rsrc_t d2 = make_buf(db + (long long)y2 * p.W, has2 ? (long long)p.W * 4 : 0);
+      const int vb = (lane < N2 ? lane * 4 : kOOB) + tz;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1)
+        a[j1] = j1 < NB ? cx{bld1(d1, vb + N2 * j1 * 4, 0), bld1(d2, vb + N2 * j1 * 4, 0)}
+                        : cx{0.f, 0.f};
+    } else if (lane < N2) {
       const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
@@ -928,14 +1007,15 @@ k_row_bfwd(RowBwdFwdArgs p) {
 // ---------------------------------------------------------------------------------------
 // Backward row pass 2: apply -D_x as its symbol, -D_y from the column pass (low columns) or
 // as a row difference (other columns), and one complex C2R per row for (dgx, dgy).
-template <int N1, int N2, int SLOTS>
+// NBO: output blocks j1 that can hold x < W (N1, or kInvHalf<N1> when 2 W <= N)
+template <int N1, int N2, int SLOTS, int NBO = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
 k_row_binv(RowBwdInvArgs p) {
   using C = RowCfg<N1, N2>;
   __shared__ float s_re[SLOTS][C::LDSC];
   __shared__ float s_im[SLOTS][C::LDSC];
-  const int slot = threadIdx.x / C::G;
-  const int lane = threadIdx.x % C::G;
+  const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
+  const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
   float* re = s_re[slot];
   float* im = s_im[slot];
   int bx, b;
@@ -999,7 +1079,19 @@ k_row_binv(RowBwdInvArgs p) {
   slot_sync();
   cx a[N1];
   inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
-  if (lane < N2 && row_ok) {
+  if constexpr (SLOTS == 1) {
+    // uniform row: descriptors whose range is that row, so stores at x >= W (and of a row
+    // outside the image) are dropped with no branch; blocks j1 >= NBO are not stored
+    const long long ro = b * p.img_out + (long long)y * p.W;
+    const long long rn = row_ok ? (long long)p.W * 4 : 0;
+    const rsrc_t ox = make_buf(p.dgx + ro, rn), oy = make_buf(p.dgy + ro, rn);
+    const int vb = (lane < N2 ? lane * 4 : kOOB) + tz;
+#pragma unroll
+    for (int j1 = 0; j1 < NBO; ++j1) {
+      bst1(ox, a[j1].x, vb + N2 * j1 * 4, 0);
+      bst1(oy, a[j1].y, vb + N2 * j1 * 4, 0);
+    }
+  } else if (lane < N2 && row_ok) {
     const int vo = (y * p.W + lane) * 4;
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) {
@@ -1035,35 +1127,40 @@ struct RowLaunch {
       if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);
       else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditNone>), grid, blk, 0, s, a);
       return hipGetLastError();
+    } else {
+      switch (a.edit) {
+        case kEditThreshold:
+          if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditThreshold>), grid, blk, 0, s, a);
+          else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditThreshold>), grid, blk, 0, s, a);
+          break;
+        case kEditGdm:
+          if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditGdm>), grid, blk, 0, s, a);
+          else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditGdm>), grid, blk, 0, s, a);
+          break;
+        case kInLaplacian:
+          if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kInLaplacian>), grid, blk, 0, s, a);
+          else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kInLaplacian>), grid, blk, 0, s, a);
+          break;
+        case kIn3D:
+          if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kIn3D>), grid, blk, 0, s, a);
+          else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kIn3D>), grid, blk, 0, s, a);
+          break;
+        default:
+          if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);
+          else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditNone>), grid, blk, 0, s, a);
+      }
+      return hipGetLastError();
     }
-    switch (a.edit) {
-      case kEditThreshold:
-        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditThreshold>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditThreshold>), grid, blk, 0, s, a);
-        break;
-      case kEditGdm:
-        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditGdm>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditGdm>), grid, blk, 0, s, a);
-        break;
-      case kInLaplacian:
-        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kInLaplacian>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kInLaplacian>), grid, blk, 0, s, a);
-        break;
-      case kIn3D:
-        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kIn3D>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kIn3D>), grid, blk, 0, s, a);
-        break;
-      default:
-        if (half) hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, NB_HALF, kEditNone>), grid, blk, 0, s, a);
-        else hipLaunchKernelGGL((k_row_fwd<N1, N2, SLOTS, N1, kEditNone>), grid, blk, 0, s, a);
-    }
-    return hipGetLastError();
   }
   static hipError_t inv(const RowInvArgs& a, int B, hipStream_t s) {
     const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
+    const bool half = 2 * a.W <= N1 * N2;
     if (a.mom)
       hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS, true>), grid, dim3(SLOTS * C::G), 0, s, a);
+    else if (half)
+      hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS, false, kInvHalf<N1>>), grid,
+                         dim3(SLOTS * C::G), 0, s, a);
     else
       hipLaunchKernelGGL((k_row_inv<N1, N2, SLOTS, false>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
@@ -1071,12 +1168,20 @@ struct RowLaunch {
   static hipError_t bfwd(const RowBwdFwdArgs& a, int B, hipStream_t s) {
     const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
-    hipLaunchKernelGGL((k_row_bfwd<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
+    if (2 * a.W <= N1 * N2)
+      hipLaunchKernelGGL((k_row_bfwd<N1, N2, SLOTS, kInvHalf<N1>>), grid, dim3(SLOTS * C::G), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((k_row_bfwd<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
   static hipError_t binv(const RowBwdInvArgs& a, int B, hipStream_t s) {
     dim3 grid((a.H + SLOTS - 1) / SLOTS, B);  // one row per slot
-    hipLaunchKernelGGL((k_row_binv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
+    if (2 * a.W <= N1 * N2)
+      hipLaunchKernelGGL((k_row_binv<N1, N2, SLOTS, kInvHalf<N1>>), grid, dim3(SLOTS * C::G), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((k_row_binv<N1, N2, SLOTS>), grid, dim3(SLOTS * C::G), 0, s, a);
     return hipGetLastError();
   }
   // half: every image of the launch has 2 W <= N
@@ -1091,9 +1196,13 @@ struct RowLaunch {
     return hipGetLastError();
   }
   static hipError_t rg_inv(const RgBase* base, const RgRowInv* tab, const RgItem* items,
-                           int nitems, hipStream_t s) {
-    hipLaunchKernelGGL((k_row_inv_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
-                       base, tab, items);
+                           int nitems, bool half, hipStream_t s) {
+    if (half)
+      hipLaunchKernelGGL((k_row_inv_rg<N1, N2, SLOTS, kInvHalf<N1>>), dim3(nitems),
+                         dim3(SLOTS * C::G), 0, s, base, tab, items);
+    else
+      hipLaunchKernelGGL((k_row_inv_rg<N1, N2, SLOTS>), dim3(nitems), dim3(SLOTS * C::G), 0, s,
+                         base, tab, items);
     return hipGetLastError();
   }
 };
@@ -1158,9 +1267,14 @@ k_row_inv_rgm(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
   p.u = base.u + e.out;
   p.partial = reinterpret_cast<const double*>(base.ws + e.red);
   const int n = p.N;
-  (void)((n == L0::N && (row_inv_body<L0::IN1, L0::IN2, L0::ISLOTS>(p, it.blk, 0, lds), true)) ||
+  // every image of a group has 2 W <= N: only the output blocks that can hold x < W
+  (void)((n == L0::N &&
+          (row_inv_body<L0::IN1, L0::IN2, L0::ISLOTS, false, kInvHalf<L0::IN1>>(p, it.blk, 0, lds),
+           true)) ||
          ... ||
-         (n == Ls::N && (row_inv_body<Ls::IN1, Ls::IN2, Ls::ISLOTS>(p, it.blk, 0, lds), true)));
+         (n == Ls::N &&
+          (row_inv_body<Ls::IN1, Ls::IN2, Ls::ISLOTS, false, kInvHalf<Ls::IN1>>(p, it.blk, 0, lds),
+           true)));
 }
 
 template <class L0, class... Ls>
