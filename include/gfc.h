@@ -80,8 +80,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream);
  * Launch geometry of a plan (speed depends on it; results only through the summation
  * order of the float64 reference term over column tiles, "col_c"). Call before
  * gfc_green_build; GFC_E_ARG for an unknown name, a value out of range, or a built plan.
- *   "row_fppw"  1..64   pairs of divergence rows handled by one FFT slot, forward row pass
- *   "row_ppw"   1..64   row pairs handled by one FFT slot in the pair-ordered row passes
  *   "col_c"     1..64   (power of two) columns per workgroup in the column pass
  *   "col_rows"  16|32   rows per thread in the forward column pass
  *   "col_rows_b" 16|32  rows per thread in the backward column pass

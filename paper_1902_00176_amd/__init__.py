@@ -196,7 +196,7 @@ def check_workspace(ws, need: int, dev, others=()):
     return ws
 
 
-PARAMS = ("row_fppw", "row_ppw", "col_c", "col_rows", "col_rows_b", "low_bins", "row_split")
+PARAMS = ("col_c", "col_rows", "col_rows_b", "low_bins", "row_split")
 _TUNING_PATH = os.path.join(_HERE, "tuning.json")
 _tuning_db = None
 

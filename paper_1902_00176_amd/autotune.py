@@ -5,8 +5,6 @@ the GPU (HIP events on the launch stream, median of several repetitions) over a 
 launch parameters, picks the fastest setting per parameter group and records it in
 tuning.json, which Plan() reads. Parameters only change speed, never results:
 
-  row_fppw   pairs of divergence rows per FFT slot in the forward row pass
-  row_ppw    row pairs per FFT slot in the pair-ordered passes  (row inverse, row backward-1)
   col_c      columns per workgroup in the column pass
   col_rows   most rows per thread in the forward column pass (16 | 32)
   col_rows_b most rows per thread in the backward column pass (16 | 32)
@@ -42,10 +40,8 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import paper_1902_00176_amd as gfc  # noqa: E402
 
-DEFAULT = {"row_fppw": 1, "row_ppw": 1, "col_c": 16, "col_rows": 16, "col_rows_b": 16}
+DEFAULT = {"col_c": 16, "col_rows": 16, "col_rows_b": 16}
 GRID = {
-    "row_fppw": [1, 2, 4],
-    "row_ppw": [1, 2, 4],
     "col": [(c, r) for c in (4, 8, 16, 32) for r in (16, 32)],
 }
 # the standard workloads: (H, W, M, N, B)
@@ -105,20 +101,6 @@ def tune_size(H, W, M, N, B, torch, verbose=True):
 
     best = dict(DEFAULT)
     log = []
-    # pairs per slot: row forward
-    res = []
-    for v in GRID["row_fppw"]:
-        t = run({**DEFAULT, "row_fppw": v})
-        res.append((t["fwd1"], v, t))
-        log.append({"row_fppw": v, **t})
-    best["row_fppw"] = min(res)[1]
-    # row pairs per slot: row inverse + row backward-1
-    res = []
-    for v in GRID["row_ppw"]:
-        t = run({**DEFAULT, "row_ppw": v})
-        res.append((t["fwd3"] + t["bwd1"], v, t))
-        log.append({"row_ppw": v, **t})
-    best["row_ppw"] = min(res)[1]
     # column pass
     res = []
     # columns per workgroup (shared) and rows per thread (forward and backward separately)

@@ -139,12 +139,11 @@ void derive_geometry(gfc_plan_s* p) {
   p->KP = (p->K + 1 + 7) / 8 * 8;
   p->gf = col_geometry(p->H + 1, p->M, p->r0, p->col_rows, p->col_c);
   p->gb = col_geometry(p->H, p->M, p->r0, p->col_rows_b, p->col_c);
-  p->nfslots = ((p->H + 2) / 2 + p->row_fppw - 1) / p->row_fppw;
+  p->nfslots = (p->H + 2) / 2;  // one pair of divergence rows per slot
   p->npairs = (p->H + 1) / 2;
   p->ntiles_f = (p->NH + p->gf.C - 1) / p->gf.C;
   p->ntiles_b = (p->NH + p->gb.C - 1) / p->gb.C;
-  const int slots_needed = (p->npairs + p->row_ppw - 1) / p->row_ppw;
-  p->nsums = (slots_needed + p->rk->bf.slots - 1) / p->rk->bf.slots;
+  p->nsums = (p->npairs + p->rk->bf.slots - 1) / p->rk->bf.slots;
 }
 
 }  // namespace
@@ -221,13 +220,7 @@ gfc_status gfc_plan_get(gfc_plan_t p, int* H, int* W, int* M, int* N, int* oy, i
 gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
   if (!p || !name) return GFC_E_ARG;
   if (p->built) return GFC_E_ARG;  // the float64 tables depend on the geometry
-  if (!std::strcmp(name, "row_fppw")) {
-    if (value < 1 || value > 64) return GFC_E_ARG;
-    p->row_fppw = value;
-  } else if (!std::strcmp(name, "row_ppw")) {
-    if (value < 1 || value > 64) return GFC_E_ARG;
-    p->row_ppw = value;
-  } else if (!std::strcmp(name, "col_c")) {
+  if (!std::strcmp(name, "col_c")) {
     if (value < 1 || value > 64 || (value & (value - 1))) return GFC_E_ARG;
     p->col_c = value;
   } else if (!std::strcmp(name, "col_rows")) {
@@ -252,9 +245,7 @@ gfc_status gfc_plan_set_param(gfc_plan_t p, const char* name, int value) {
 
 gfc_status gfc_plan_get_param(gfc_plan_t p, const char* name, int* value) {
   if (!p || !name || !value) return GFC_E_ARG;
-  if (!std::strcmp(name, "row_fppw")) *value = p->row_fppw;
-  else if (!std::strcmp(name, "row_ppw")) *value = p->row_ppw;
-  else if (!std::strcmp(name, "col_c")) *value = p->gf.C;
+  if (!std::strcmp(name, "col_c")) *value = p->gf.C;
   else if (!std::strcmp(name, "col_rows")) *value = p->col_rows;
   else if (!std::strcmp(name, "col_rows_b")) *value = p->col_rows_b;
   else if (!std::strcmp(name, "low_bins")) *value = p->K;
@@ -298,7 +289,7 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   const std::vector<f2> twA = tw_fwd(p->rk->f), twAe = tw_fwd(p->rk->e);
   const std::vector<f2> twB = tw_inv(p->rk->i);
   const std::vector<f2> twAb = tw_fwd(p->rk->bf), twBb = tw_inv(p->rk->bi);
-  std::vector<f2> sxm(NH), dsh(NH);
+  std::vector<f2> dsh(NH);
   // low-bin twiddles of a forward row pass, lane j < N2 of a G-lane slot:
   // [0][l][j] = (1 - w_N^l) w_N^(l j) for Ex, [1][l][j] = w_N^(l j) for Ey (0 for j >= N2)
   const int K1 = kLowBins + 1;
@@ -335,10 +326,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   }
   for (int l = 0; l < NH; ++l) {
     double c, s;
-    cs2pi(l, N, c, s);
-    const double h = std::sin(kPi * double(l) / double(N));
-    const double omc = 2.0 * h * h;  // 1 - cos(2 pi l / N)
-    sxm[l] = f2{float(omc), float(-s)};  // 1 - e^{+i theta}
     cs2pi(long(l) * p->c0, N, c, s);
     dsh[l] = f2{float(c), float(-s)};    // e^{-2 pi i l c0 / N}
   }
@@ -363,7 +350,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   const size_t o_twAe = off; off = align256(off + twAe.size() * sizeof(f2));
   const size_t o_twLe = off; off = align256(off + twLe.size() * sizeof(f2));
   const size_t o_twX = off; off = align256(off + twX.size() * sizeof(f2));
-  const size_t o_sxm = off; off = align256(off + sxm.size() * sizeof(f2));
   const size_t o_dsh = off; off = align256(off + dsh.size() * sizeof(f2));
   const size_t o_ccf = off; off = align256(off + ccf.size() * sizeof(ColConst));
   const size_t o_ccb = off; off = align256(off + ccb.size() * sizeof(ColConst));
@@ -377,7 +363,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   std::memcpy(host.data() + o_twAe, twAe.data(), twAe.size() * sizeof(f2));
   std::memcpy(host.data() + o_twLe, twLe.data(), twLe.size() * sizeof(f2));
   std::memcpy(host.data() + o_twX, twX.data(), twX.size() * sizeof(f2));
-  std::memcpy(host.data() + o_sxm, sxm.data(), sxm.size() * sizeof(f2));
   std::memcpy(host.data() + o_dsh, dsh.data(), dsh.size() * sizeof(f2));
   std::memcpy(host.data() + o_ccf, ccf.data(), ccf.size() * sizeof(ColConst));
   std::memcpy(host.data() + o_ccb, ccb.data(), ccb.size() * sizeof(ColConst));
@@ -401,7 +386,6 @@ gfc_status gfc_green_build(gfc_plan_t p, void* stream) {
   p->twAe = reinterpret_cast<f2*>(base + o_twAe);
   p->twLe = reinterpret_cast<f2*>(base + o_twLe);
   p->twX = reinterpret_cast<f2*>(base + o_twX);
-  p->sxm = reinterpret_cast<f2*>(base + o_sxm);
   p->dshift = reinterpret_cast<f2*>(base + o_dsh);
   p->ccf = reinterpret_cast<ColConst*>(base + o_ccf);
   p->ccb = reinterpret_cast<ColConst*>(base + o_ccb);
@@ -596,7 +580,6 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     a.H = p->H;
     a.W = p->W;
     a.npairs = (p->H + 1) / 2;
-    a.ppw = p->row_ppw;
     a.img_in = (long long)p->H * p->W;
     a.img_u = img_t;
     const gfc_status st = hip_status(p->rk->bfwd(a, B, s));
@@ -635,7 +618,6 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     v.dgx = dgx;
     v.dgy = dgy;
     v.twB = p->twBb;
-    v.sxm = p->sxm;
     v.H = p->H;
     v.W = p->W;
     v.Kb = p->Kb;

@@ -23,18 +23,27 @@ struct f2b {
   float x, y;
 };
 
+// Cache-policy operand of an access: 0 is the default; kNT marks it nontemporal (streamed
+// through the caches with low retention). A pass that reads a block once and writes it
+// once moves its bytes faster when both its loads and its stores carry kNT.
+constexpr int kNT = 2;
+
+template <int CP = 0>
 __device__ __forceinline__ f2b bld2(rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(f2b, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  return __builtin_bit_cast(f2b, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ float bld1(rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ void bst2(rsrc_t r, float x, float y, int voff, int soff) {
   using v2u = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, f2b{x, y}), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, f2b{x, y}), r, voff, soff, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void bst1(rsrc_t r, float x, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, CP);
 }
 
 }  // namespace gfc

@@ -140,7 +140,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   // ---- 1. load the segment, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
-  for (int j = 0; j < LMAX; ++j) v[j] = bld2(rT, vX + j * rowT, 0);
+  for (int j = 0; j < LMAX; ++j) v[j] = bld2<kNT>(rT, vX + j * rowT, 0);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (LOWTILE && low) {
     const rsrc_t rS = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
@@ -256,7 +256,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
         pin(v[j]);
         const double y = double(p0 + j);
         const double val = (D.x + double(v[j].x) - bbar * y) * outs;
-        bst2(rT, float(val), 0.f, vS3 + j * rowT, 0);
+        bst2<kNT>(rT, float(val), 0.f, vS3 + j * rowT, 0);
       }
     } else {
       const int kseg = kp->kseg;
@@ -278,7 +278,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
         const dc w = dfma(pj, D, dc{v[j].x, v[j].y});
         if (TAIL) z = dsel(j < Ls, dfma(rho, z, w), z);
         else z = dfma(rho, z, w);
-        bst2(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
+        bst2<kNT>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
         pj *= inv_rho;
       }
     }
@@ -364,7 +364,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   // ---- 1. load, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
-  for (int j = 0; j < LMAX; ++j) v[j] = bld2(rIn, vT + j * rowT, 0);
+  for (int j = 0; j < LMAX; ++j) v[j] = bld2<kNT>(rIn, vT + j * rowT, 0);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (dcol) {
     // column 0: inclusive prefix sums of x, and the sum of those prefixes over the segment
@@ -467,7 +467,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
         pin(v[j]);
         const double P = D.x + double(v[j].x) - xbar * double(p0 + j + 1);
         bst2(rD, float(-(P - meanP) * outs), 0.f, vD3 + j * rowD, 0);
-        bst2(rT, 0.f, 0.f, vS3 + j * rowT, 0);
+        bst2<kNT>(rT, 0.f, 0.f, vS3 + j * rowT, 0);
       }
       if (s == last) bst2(rT, 0.f, 0.f, vEnd, 0);
     } else {
@@ -490,7 +490,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
         }
         if (TAIL) z = dsel(j < Ls, dfma(rho, z, w), z);
         else z = dfma(rho, z, w);
-        bst2(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
+        bst2<kNT>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
         pj *= inv_rho;
       }
     }

@@ -38,7 +38,6 @@ struct RowFwdArgs {
   const f2* twX;      // [N + kMaxLowBins + 1]: w_N^m (m < N), then 1 - w_N^l (l <= kMaxLowBins)
   int H, W, K, KP;
   int N, NHP;         // row length and T1 row stride (used by launch_low_ext)
-  int ppw;            // pairs of L rows per slot
   int npairs;         // ceil((H+1) / 2)
   long long img_in, img_t1, img_sb;
   // volumes (kIn3D): the launch's image index runs over (volume, z) with z in [0, zd]; gx,
@@ -58,7 +57,6 @@ struct RowInvArgs {
   const f2* twB;      // [N2][N1]: w_N^(k j2), forward sign, conjugated in use
   int H, W;
   int npairs;         // ceil(H / 2)
-  int ppw;            // row pairs per slot
   long long img_t2, img_u;
   double* mom;        // [B][gridDim.x][2]: sums of u and u^2 per workgroup, or null
   // volumes: the image index runs over (volume, z), z < zd; T2 planes [B][zp][H+1][NHP],
@@ -102,7 +100,6 @@ struct RowBwdFwdArgs {
   const f2* twA;
   int H, W;
   int npairs;
-  int ppw;
   long long img_in, img_u;
 };
 
@@ -117,7 +114,6 @@ struct RowBwdInvArgs {
   float* dgx;
   float* dgy;
   const f2* twB;
-  const f2* sxm;      // [NH]: 1 - w_N^-l
   int H, W, Kb, KbP;
   long long img_w, img_sd, img_out;
 };

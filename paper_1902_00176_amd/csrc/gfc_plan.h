@@ -13,11 +13,9 @@
 namespace gfc {
 
 // Launch geometry defaults; each can be changed per plan with gfc_plan_set_param.
-constexpr int kFwdPairsPerSlot = 1;  // "row_fppw": pairs of L rows per slot, forward row pass
 constexpr int kColC = 16;         // "col_c": columns per workgroup in the column pass
 constexpr int kColRows = 16;      // "col_rows", "col_rows_b": rows per thread in the forward
                                   // and the backward column pass (16|32)
-constexpr int kPairsPerSlot = 1;  // "row_ppw": row pairs per slot in the pair-ordered passes
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -32,8 +30,7 @@ struct gfc_plan_s {
   const gfc::RowKernels* rk = nullptr;
   gfc::ColGeom gf{}, gb{};
   // launch geometry (gfc_plan_set_param) and what follows from it
-  int row_fppw = gfc::kFwdPairsPerSlot, row_ppw = gfc::kPairsPerSlot, col_c = gfc::kColC,
-      col_rows = gfc::kColRows, col_rows_b = gfc::kColRows;
+  int col_c = gfc::kColC, col_rows = gfc::kColRows, col_rows_b = gfc::kColRows;
   int nfslots = 0, npairs = 0;
   int ntiles_f = 0, ntiles_b = 0, nsums = 0;
   // device tables, one allocation (gfc_green_build)
@@ -44,7 +41,7 @@ struct gfc_plan_s {
   // modes, twB inverse, twAb backward forward, twBb backward inverse; twL / twLe the low-bin
   // lane factors of the two forward splits
   gfc::f2 *twA = nullptr, *twAe = nullptr, *twB = nullptr, *twAb = nullptr, *twBb = nullptr,
-          *twL = nullptr, *twLe = nullptr, *twX = nullptr, *sxm = nullptr, *dshift = nullptr;
+          *twL = nullptr, *twLe = nullptr, *twX = nullptr, *dshift = nullptr;
   double* twD = nullptr;  // [N][2] float64 w_N^m (direct sums of a given Laplacian's low bins)
   gfc::ColConst *ccf = nullptr, *ccb = nullptr;
   // a side stream for the forward column pass's low tiles, joined back with two events
@@ -59,7 +56,7 @@ namespace gfc {
 
 // workgroups of the inverse row pass (one moment pair each for the colour correction)
 inline int inv_groups(const gfc_plan_s* p) {
-  const int slots_needed = ((p->H + 1) / 2 + p->row_ppw - 1) / p->row_ppw;
+  const int slots_needed = (p->H + 1) / 2;  // one row pair per slot
   return (slots_needed + p->rk->i.slots - 1) / p->rk->i.slots;
 }
 
@@ -107,7 +104,6 @@ inline RowFwdArgs row_fwd_args(const gfc_plan_s* p, const float* gx, const float
   a.KP = p->KP;
   a.N = p->N;
   a.NHP = p->NHP;
-  a.ppw = p->row_fppw;
   a.npairs = (p->H + 2) / 2;
   a.img_in = (long long)p->H * p->W;
   a.img_t1 = (long long)(p->H + 1) * p->NHP;
@@ -155,7 +151,6 @@ inline RowInvArgs row_inv_args(const gfc_plan_s* p, const f2* T, float* u,
   v.H = p->H;
   v.W = p->W;
   v.npairs = (p->H + 1) / 2;
-  v.ppw = p->row_ppw;
   v.img_t2 = (long long)(p->H + 1) * p->NHP;
   v.img_u = (long long)p->H * p->W;
   v.mom = nullptr;

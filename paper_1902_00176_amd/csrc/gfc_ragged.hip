@@ -326,8 +326,7 @@ gfc_status gfc_ragged_build(gfc_ragged_t r, void* stream) {
     for (int i : ch) {
       const gfc_plan_s* p = r->plans[r->plan_of[i]];
       const int slots = p->rk->i.slots;
-      const int need = (p->npairs + p->row_ppw - 1) / p->row_ppw;
-      const int nb = (need + slots - 1) / slots;
+      const int nb = (p->npairs + slots - 1) / slots;
       for (int k = 0; k < nb; ++k) items.push_back(RgItem{i, k});
     }
     g.i_n = int(items.size()) - g.i_off;

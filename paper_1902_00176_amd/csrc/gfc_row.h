@@ -9,6 +9,11 @@
 // The small DFTs are register-resident (gfc_dft.h). Real-signal handling: two real
 // sequences share one complex FFT (packing a + i b), separated by the mirror bins N - l
 // through a second LDS pass in natural order.
+// Every exchange goes through a single LDS plane per slot, real parts first and then the
+// imaginary parts: at N = 2400 that is 9.8 KB instead of 19.7 KB, and together with
+// register budgets under 168 it lets three wavefronts share a SIMD instead of two (the row
+// passes wait on memory and LDS, and the third wavefront hides those waits: 20-25 % off
+// the inverse passes). Spectra are read and written in natural bin order, coalesced.
 #pragma once
 #include "gfc_buf.h"
 #include "gfc_dft.h"
@@ -73,58 +78,69 @@ __device__ __forceinline__ int fresh_zero() {
   return z;
 }
 
-// Forward four-step body. On entry lane j < N2 holds a[y1] = z[N2*y1 + j]; on exit the
-// spectrum Z is in LDS (re/im planes) in natural order.
+// The forward four-step through one LDS plane (real parts, then imaginary parts). On entry
+// lane j < N2 holds a[y1] = z[N2*y1 + j]; on exit lane k < N1 holds b[k2] = Z[k + N1*k2]
+// and the plane is free (the caller exchanges the spectrum from there).
 template <int N1, int N2, bool EXACT_TW = false>
-__device__ __forceinline__ void fwd_fft_to_lds(cx (&a)[N1], float* re, float* im, int lane,
-                                               rsrc_t twA, int tz) {
+__device__ __forceinline__ void fwd_fft_1p(cx (&a)[N1], cx (&b)[N2], float* pl, int lane,
+                                           rsrc_t twA, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N2) {
     DftSel<N1, -1>::run(a);
     twiddles<N1, N2, EXACT_TW>(twA, lane, tz, [&](int k1, cx w) { a[k1] = cmul(a[k1], w); });
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      re[k1 * C::SA + lane] = a[k1].x;
-      im[k1 * C::SA + lane] = a[k1].y;
-    }
+    for (int k1 = 0; k1 < N1; ++k1) pl[k1 * C::SA + lane] = a[k1].x;
   }
   slot_sync();
-  cx b[N2];
   if (lane < N1) {
 #pragma unroll
-    for (int j = 0; j < N2; ++j) b[j] = {re[lane * C::SA + j], im[lane * C::SA + j]};
+    for (int j = 0; j < N2; ++j) b[j].x = pl[lane * C::SA + j];
+  }
+  slot_sync();
+  if (lane < N2) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) pl[k1 * C::SA + lane] = a[k1].y;
+  }
+  slot_sync();
+  if (lane < N1) {
+#pragma unroll
+    for (int j = 0; j < N2; ++j) b[j].y = pl[lane * C::SA + j];
+    // the transform starts once both halves are in: arithmetic on the real parts hoisted
+    // above the exchange of the imaginary parts would hold both live
+#pragma unroll
+    for (int j = 0; j < N2; ++j) asm volatile("" : "+v"(b[j].x), "+v"(b[j].y));
     DftSel<N2, -1>::run(b);
-  }
-  slot_sync();
-  if (lane < N1) {
-#pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
-      re[lane + N1 * k2] = b[k2].x;
-      im[lane + N1 * k2] = b[k2].y;
-    }
   }
   slot_sync();
 }
 
-// Inverse four-step body. On entry lane k < N1 holds b[k2] = Z[k + N1*k2]; on exit lane
-// j < N2 holds a[j1] = z[j + N2*j1] (unnormalised inverse DFT).
+// Inverse four-step body through one LDS plane (real parts, then imaginary parts). On entry
+// lane k < N1 holds b[k2] = Z[k + N1*k2]; on exit lane j < N2 holds a[j1] = z[j + N2*j1]
+// (unnormalised inverse DFT).
 template <int N1, int N2>
-__device__ __forceinline__ void inv_fft_from_regs(cx (&b)[N2], cx (&a)[N1], float* re,
-                                                  float* im, int lane, rsrc_t twB, int tz) {
+__device__ __forceinline__ void inv_fft_from_regs_1p(cx (&b)[N2], cx (&a)[N1], float* pl,
+                                                     int lane, rsrc_t twB, int tz) {
   using C = RowCfg<N1, N2>;
   if (lane < N1) {
     DftSel<N2, +1>::run(b);
     twiddles<N2, N1>(twB, lane, tz, [&](int j2, cx w) { b[j2] = cmulconj(b[j2], w); });
 #pragma unroll
-    for (int j2 = 0; j2 < N2; ++j2) {
-      re[j2 * C::SB + lane] = b[j2].x;
-      im[j2 * C::SB + lane] = b[j2].y;
-    }
+    for (int j2 = 0; j2 < N2; ++j2) pl[j2 * C::SB + lane] = b[j2].x;
   }
   slot_sync();
   if (lane < N2) {
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) a[k1] = {re[lane * C::SB + k1], im[lane * C::SB + k1]};
+    for (int k1 = 0; k1 < N1; ++k1) a[k1].x = pl[lane * C::SB + k1];
+  }
+  slot_sync();
+  if (lane < N1) {
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) pl[j2 * C::SB + lane] = b[j2].y;
+  }
+  slot_sync();
+  if (lane < N2) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) a[k1].y = pl[lane * C::SB + k1];
     DftSel<N1, +1>::run(a);
   }
 }
@@ -452,19 +468,19 @@ __device__ __forceinline__ void low_lane_factors(cx (&ax0)[kLowBins], cx (&ax1)[
 }
 
 // LDS floats of one slot's plane in the forward row pass: the FFT exchange, or the low-bin
-// lane sums (4 (2K + 1) values over G + 1 lanes) when larger
+// lane sums (4 (2K + 1) values at a stride of G + 1 lanes) when larger
 template <int N1, int N2>
 constexpr int kFwdPlane =
-    cmax(RowCfg<N1, N2>::LDSC, (4 * (2 * kLowBins + 1) * (RowCfg<N1, N2>::G + 1) + 1) / 2);
+    cmax(RowCfg<N1, N2>::LDSC, 4 * (2 * kLowBins + 1) * (RowCfg<N1, N2>::G + 1));
 // volume slices also sum Ez: 3K + 2 complex low-bin values per row
 template <int N1, int N2>
 constexpr int kFwdPlane3 =
-    cmax(RowCfg<N1, N2>::LDSC, (4 * (3 * kLowBins + 2) * (RowCfg<N1, N2>::G + 1) + 1) / 2);
+    cmax(RowCfg<N1, N2>::LDSC, 4 * (3 * kLowBins + 2) * (RowCfg<N1, N2>::G + 1));
 template <int N1, int N2, int SLOTS, int EDIT = kEditNone>
-constexpr int kFwdLds =  // floats per workgroup
-    SLOTS * 2 * (EDIT == kIn3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>);
+constexpr int kFwdLds =  // floats per workgroup: one plane per slot
+    SLOTS * (EDIT == kIn3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>);
 template <int N1, int N2, int SLOTS>
-constexpr int kInvLds = SLOTS * 2 * RowCfg<N1, N2>::LDSC;
+constexpr int kInvLds = SLOTS * RowCfg<N1, N2>::LDSC;  // one plane per slot
 
 // lds: kFwdLds<N1, N2, SLOTS> floats of the workgroup's LDS
 template <int N1, int N2, int SLOTS, int NB, int EDIT = kEditNone>
@@ -477,10 +493,10 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
   constexpr int NV = 4 * NC;             // floats per lane to sum: two rows, re and im
   constexpr int RS = C::G + 1;           // LDS stride of one value over the lanes
   constexpr int PLANE = IS3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>;
+  static_assert(NV * RS <= PLANE, "the low-bin lane sums fit the slot's plane");
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
-  float* re = lds + slot * 2 * PLANE;
-  float* im = re + PLANE;
+  float* pl = lds + slot * PLANE;
   const float* gxi = p.gx + b * p.img_in;
   const float* gyi = p.gy + b * p.img_in;
   // volumes: b runs over (volume, z <= zd); the T1 plane is z of zp
@@ -500,9 +516,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
   const rsrc_t rgx = make_buf(gxi, p.img_in * 4);
   const rsrc_t rgy = make_buf(gyi, p.img_in * 4);
 
-  for (int r = 0; r < p.ppw; ++r) {
+  {
     const int tz = fresh_zero();
-    const int q = (bx * SLOTS + slot) * p.ppw + r;
+    const int q = bx * SLOTS + slot;
     const bool ok = q < p.npairs;
     const int y0 = 2 * q;
     cx a[N1];
@@ -641,10 +657,10 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
                            : c < E2 ? ay0[c < E2 ? c - KL : 0] : az0[c < E2 ? 0 : c - E2];
       const cx v1 = c < KL ? ax1[c < KL ? c : 0]
                            : c < E2 ? ay1[c < E2 ? c - KL : 0] : az1[c < E2 ? 0 : c - E2];
-      re[(2 * c) * RS + lane] = v0.x;
-      re[(2 * c + 1) * RS + lane] = v0.y;
-      re[(2 * NC + 2 * c) * RS + lane] = v1.x;
-      re[(2 * NC + 2 * c + 1) * RS + lane] = v1.y;
+      pl[(2 * c) * RS + lane] = v0.x;
+      pl[(2 * c + 1) * RS + lane] = v0.y;
+      pl[(2 * NC + 2 * c) * RS + lane] = v1.x;
+      pl[(2 * NC + 2 * c + 1) * RS + lane] = v1.y;
     }
     slot_sync();
     // lane t sums values t, t + G, ... over the N2 lanes that hold elements
@@ -654,16 +670,39 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
       const int v = lane + C::G * k;
       if (v < NV) {
 #pragma unroll
-        for (int j = 0; j < N2; ++j) lowsum[k] += re[v * RS + j];
+        for (int j = 0; j < N2; ++j) lowsum[k] += pl[v * RS + j];
       }
     }
     slot_sync();
     }  // !FULLBINS
 
-    fwd_fft_to_lds<N1, N2, FULLBINS || IS3D>(a, re, im, lane, rtw, tz);
+    cx z[N2];
+    fwd_fft_1p<N1, N2, FULLBINS || IS3D>(a, z, pl, lane, rtw, tz);
 
     // Z = FFT(L[y0] + i L[y0+1]): L^[y0, l] = (Z[l] + conj Z[N-l]) / 2,
-    // L^[y0+1, l] = (Z[l] - conj Z[N-l]) / 2i; bins l <= K come from the direct sums
+    // L^[y0+1, l] = (Z[l] - conj Z[N-l]) / 2i; bins l <= K come from the direct sums.
+    // Z reaches natural order through the plane, real parts (bins l and N - l of the
+    // lane) first, then the imaginary parts, read where they are used.
+    float zr[C::NI], zm[C::NI];
+    if (lane < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) pl[lane + N1 * k2] = z[k2].x;
+    }
+    slot_sync();
+#pragma unroll
+    for (int i = 0; i < C::NI; ++i) {
+      const int l = lane + C::G * i;
+      const bool inside = C::G * i + C::G - 1 < C::NH ? true : l < C::NH;
+      const int m = (i == 0 && lane == 0) || !inside ? 0 : C::N - l;
+      zr[i] = pl[inside ? l : 0];
+      zm[i] = pl[m];
+    }
+    slot_sync();
+    if (lane < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) pl[lane + N1 * k2] = z[k2].y;
+    }
+    slot_sync();
     const bool has1 = ok && y0 + 1 <= p.H;
     if constexpr (SLOTS == 1) {
       // uniform rows: a descriptor per T1 row with range NH bins (empty outside the image),
@@ -677,7 +716,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         // mirror bin N - l (0 for l = 0, and for lanes past NH whose stores are dropped)
         const bool inside = C::G * i + C::G - 1 < C::NH ? true : l < C::NH;
         const int m = (i == 0 && lane == 0) || !inside ? 0 : C::N - l;
-        const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
+        const float ar = zr[i], ai = pl[inside ? l : 0], br = zm[i], bi = pl[m];
         cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
         cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
         int off = (lane + C::G * i) * 8 + tz;
@@ -700,7 +739,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         // their split form (launch_lap_low); volumes build theirs after the z transform
         if (ok && l < C::NH) {
           const int m = (l == 0) ? 0 : C::N - l;
-          const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
+          const float ar = zr[i], ai = pl[l], br = zm[i], bi = pl[m];
           const cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
           const cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
           bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
@@ -708,7 +747,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         }
       } else if (ok && l < C::NH && (l == 0 || l > KL)) {
         const int m = (l == 0) ? 0 : C::N - l;
-        const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
+        const float ar = zr[i], ai = pl[l], br = zm[i], bi = pl[m];
         cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
         cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
         if (l == 0) A = B = {0.f, 0.f};  // (1 - w_N^0) Ex^ = 0; Ey^ goes to SB
@@ -774,13 +813,52 @@ k_row_fwd_rg(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
 
 // ---------------------------------------------------------------------------------------
 // Inverse row pass (row C2R of eq. (23), real part, crop and Algorithm B's constant).
-// Each slot handles p.ppw pairs of rows, two rows per complex inverse FFT.
+// Each slot handles one pair of rows, two rows per complex inverse FFT.
 // MOM: also the float64 sums of the stored values and their squares, one pair per
 // workgroup (fixed summation order), for the colour correction of eq. (25).
 // lds: kInvLds<N1, N2, SLOTS> floats of the workgroup's LDS
 // Output blocks j1 of the inverse row pass that can hold x = lane + N2 j1 < W when 2 W <= N
 template <int N1>
 constexpr int kInvHalf = (N1 + 1) / 2;
+
+// Packed spectrum of two real rows, P = F(r1) + i F(r2), from their half spectra X1, X2 at
+// the bins l = lane + G q < NH that the lane holds: P[l] = (X1.x - X2.y, X1.y + X2.x) and
+// P[N - l] = (X1.x + X2.y, X2.x - X1.y). The bins go through one LDS plane, real parts
+// first, and come out in the four-step layout: lane k < N1 gets bz[k2] = P[k + N1 k2].
+template <int N1, int N2>
+__device__ __forceinline__ void packed_to_bz(const cx (&X1)[RowCfg<N1, N2>::NI],
+                                             const cx (&X2)[RowCfg<N1, N2>::NI],
+                                             cx (&bz)[N2], float* pl, int lane) {
+  using C = RowCfg<N1, N2>;
+#pragma unroll
+  for (int q = 0; q < C::NI; ++q) {
+    const int l = lane + C::G * q;
+    if (l < C::NH) {
+      pl[l] = X1[q].x - X2[q].y;
+      if (l != 0 && 2 * l != C::N) pl[C::N - l] = X1[q].x + X2[q].y;
+    }
+  }
+  slot_sync();
+  if (lane < N1) {
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) bz[k2].x = pl[lane + N1 * k2];
+  }
+  slot_sync();
+#pragma unroll
+  for (int q = 0; q < C::NI; ++q) {
+    const int l = lane + C::G * q;
+    if (l < C::NH) {
+      pl[l] = X1[q].y + X2[q].x;
+      if (l != 0 && 2 * l != C::N) pl[C::N - l] = X2[q].x - X1[q].y;
+    }
+  }
+  slot_sync();
+  if (lane < N1) {
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) bz[k2].y = pl[lane + N1 * k2];
+  }
+  slot_sync();
+}
 
 // NBO: output blocks j1 that can hold x < W (N1, or kInvHalf<N1> when 2 W <= N)
 template <int N1, int N2, int SLOTS, bool MOM = false, int NBO = N1>
@@ -790,11 +868,10 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
   double m1 = 0.0, m2 = 0.0;
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
-  float* re = lds + slot * C::LDSC;
-  float* im = lds + (SLOTS + slot) * C::LDSC;
+  float* pl = lds + slot * C::LDSC;
   // image b, or slice z = b % zd of volume b / zd (its spectra are plane z of zp)
   const int vol = b / p.zd;
-  const rsrc_t rT2 = make_buf(p.T2 + ((long long)vol * p.zp + b % p.zd) * p.img_t2, p.img_t2 * 8);
+  const f2* T2i = p.T2 + ((long long)vol * p.zp + b % p.zd) * p.img_t2;
   const rsrc_t ru = make_buf(p.u + b * p.img_u, p.img_u * 4);
   const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
 
@@ -806,48 +883,34 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
   for (int off = C::G / 2; off > 0; off >>= 1) vr += __shfl_xor(vr, off, C::G);
   const float vref = float(vr);
 
-  for (int r = 0; r < p.ppw; ++r) {
+  {
     const int tz = fresh_zero();
-    const int q = (bx * SLOTS + slot) * p.ppw + r;
+    const int q = bx * SLOTS + slot;
     const bool ok = q < p.npairs;
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
-    if constexpr (SLOTS == 1 && !MOM) {
-      // One slot per wavefront: the rows are uniform, and each output row gets a descriptor
-      // whose range is that row (empty outside the image): stores at x >= W are dropped by
-      // the hardware, so no element needs a branch; blocks j1 >= NBO hold no x < W and are
-      // not stored at all.
-      // (the spectrum loads keep their uniform branches on the row pair: without them the
-      // compiler issued the loads two at a time, each pair followed by a full wait)
-      cx bz[N2];
-      if (lane < N1) {
-#pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-          const int kk = lane + N1 * k2;
-          const int m = kk < C::NH ? kk : C::N - kk;
-          f2b X1 = {0.f, 0.f}, X2 = {0.f, 0.f};
-          if (ok) X1 = bld2(rT2, (y1 * C::NHP + m) * 8, 0);
-          if (has2) X2 = bld2(rT2, (y2 * C::NHP + m) * 8, 0);
-          if (kk < C::NH) bz[k2] = {X1.x - X2.y, X1.y + X2.x};
-          else bz[k2] = {X1.x + X2.y, X2.x - X1.y};
-        }
-      }
-      cx a[N1];
-      inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
-      const float* ub = p.u + b * p.img_u;
-      const rsrc_t u1 = make_buf(ub + (long long)y1 * p.W, ok ? (long long)p.W * 4 : 0);
-      const rsrc_t u2 = make_buf(ub + (long long)y2 * p.W, has2 ? (long long)p.W * 4 : 0);
-      const int vb = (lane < N2 ? lane * 4 : kOOB) + tz;
-#pragma unroll
-      for (int j1 = 0; j1 < NBO; ++j1) {
-        bst1(u1, a[j1].x - vref, vb + N2 * j1 * 4, 0);
-        bst1(u2, a[j1].y - vref, vb + N2 * j1 * 4, 0);
-      }
-      slot_sync();
-      continue;
-    }
     cx bz[N2];
-    if (lane < N1) {
+    if constexpr (SLOTS == 1) {
+      // One slot per wavefront: the rows are uniform and each has a descriptor whose range
+      // is that row, empty outside the image. The spectrum bins are read in natural order
+      // (coalesced; bins >= NH and missing rows read 0) and reach the four-step layout
+      // through LDS.
+      const rsrc_t r1 = make_buf(T2i + (long long)y1 * C::NHP, ok ? C::NH * 8 : 0);
+      const rsrc_t r2 = make_buf(T2i + (long long)y2 * C::NHP, has2 ? C::NH * 8 : 0);
+      cx X1[C::NI], X2[C::NI];
+#pragma unroll
+      for (int i = 0; i < C::NI; ++i) {
+        // the bin in the per-lane offset, so that the range check covers it
+        const f2b v1 = bld2(r1, (lane + C::G * i + tz) * 8, 0);
+        const f2b v2 = bld2(r2, (lane + C::G * i + tz) * 8, 0);
+        X1[i] = {v1.x, v1.y};
+        X2[i] = {v2.x, v2.y};
+      }
+      packed_to_bz<N1, N2>(X1, X2, bz, pl, lane);
+    } else if (lane < N1) {
+      // slots of one wavefront hold different rows: one descriptor for the image, and lane
+      // k gathers its bins k + N1 k2 (from the Hermitian mirror past N/2) directly
+      const rsrc_t rT2 = make_buf(T2i, p.img_t2 * 8);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
         const int kk = lane + N1 * k2;
@@ -860,8 +923,20 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
       }
     }
     cx a[N1];
-    inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
-    if (lane < N2 && ok) {
+    inv_fft_from_regs_1p<N1, N2>(bz, a, pl, lane, rtw, tz);
+    if constexpr (SLOTS == 1 && !MOM) {
+      // output rows with descriptors whose range is the row: stores at x >= W are dropped
+      // by the hardware with no branch; blocks j1 >= NBO hold no x < W and are not stored
+      const float* ub = p.u + b * p.img_u;
+      const rsrc_t u1 = make_buf(ub + (long long)y1 * p.W, ok ? (long long)p.W * 4 : 0);
+      const rsrc_t u2 = make_buf(ub + (long long)y2 * p.W, has2 ? (long long)p.W * 4 : 0);
+      const int vb = (lane < N2 ? lane * 4 : kOOB) + tz;
+#pragma unroll
+      for (int j1 = 0; j1 < NBO; ++j1) {
+        bst1(u1, a[j1].x - vref, vb + N2 * j1 * 4, 0);
+        bst1(u2, a[j1].y - vref, vb + N2 * j1 * 4, 0);
+      }
+    } else if (lane < N2 && ok) {
       const int v1 = (y1 * p.W + lane) * 4, v2 = (y2 * p.W + lane) * 4;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
@@ -906,7 +981,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
 
 template <int N1, int N2, int SLOTS, bool MOM, int NBO = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_inv(RowInvArgs p) {
+__attribute__((amdgpu_waves_per_eu(3))) k_row_inv(RowInvArgs p) {
   __shared__ float lds[kInvLds<N1, N2, SLOTS>];
   row_inv_body<N1, N2, SLOTS, MOM, NBO>(p, blockIdx.x, blockIdx.y, lds);
 }
@@ -930,24 +1005,22 @@ k_row_inv_rg(const RgBase* basep, const RgRowInv* tab, const RgItem* items) {
 // NB: input blocks j1 that can hold x < W (N1, or kInvHalf<N1> when 2 W <= N)
 template <int N1, int N2, int SLOTS, int NB = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_bfwd(RowBwdFwdArgs p) {
+__attribute__((amdgpu_waves_per_eu(3))) k_row_bfwd(RowBwdFwdArgs p) {
   using C = RowCfg<N1, N2>;
-  __shared__ float s_re[SLOTS][C::LDSC];
-  __shared__ float s_im[SLOTS][C::LDSC];
+  __shared__ float s_pl[SLOTS][C::LDSC];  // one plane: real parts cross, then imaginary
   __shared__ double s_sum[SLOTS];
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
-  float* re = s_re[slot];
-  float* im = s_im[slot];
+  float* pl = s_pl[slot];
   const int b = blockIdx.y;
   const rsrc_t rdu = make_buf(p.du + b * p.img_in, p.img_in * 4);
   const rsrc_t rU = make_buf(p.U + b * p.img_u, p.img_u * 8);
   const rsrc_t rtw = make_buf(p.twA, (long long)C::N * 8);
 
   double lsum = 0.0;
-  for (int r = 0; r < p.ppw; ++r) {
+  {
     const int tz = fresh_zero();
-    const int q = (blockIdx.x * SLOTS + slot) * p.ppw + r;
+    const int q = blockIdx.x * SLOTS + slot;
     const bool ok = q < p.npairs;
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
@@ -974,19 +1047,42 @@ k_row_bfwd(RowBwdFwdArgs p) {
         a[j1] = {e1, e2};
       }
     }
-    fwd_fft_to_lds<N1, N2>(a, re, im, lane, rtw, tz);
+    cx z[N2];
+    fwd_fft_1p<N1, N2>(a, z, pl, lane, rtw, tz);
+    // bins l and m = N - l of the packed transform, real parts first
+    float ar[C::NI], br[C::NI];
+    if (lane < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) pl[lane + N1 * k2] = z[k2].x;
+    }
+    slot_sync();
+#pragma unroll
+    for (int i = 0; i < C::NI; ++i) {
+      const int l = lane + C::G * i;
+      const int m = (l == 0) ? 0 : C::N - l;
+      ar[i] = l < C::NH ? pl[l] : 0.f;
+      br[i] = l < C::NH ? pl[m] : 0.f;
+    }
+    slot_sync();
+    if (lane < N1) {
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) pl[lane + N1 * k2] = z[k2].y;
+    }
+    slot_sync();
     // the DC bin of the packed transform is (sum of row y1) + i (sum of row y2)
-    if (lane == 0) lsum += double(re[0]) + double(im[0]);
+    if (lane == 0) lsum += double(ar[0]) + double(pl[0]);
     if (ok) {
 #pragma unroll
       for (int i = 0; i < C::NI; ++i) {
         const int l = lane + C::G * i;
         if (l < C::NH) {
           const int m = (l == 0) ? 0 : C::N - l;
-          const float ar = re[l], ai = im[l], br = re[m], bi = im[m];
-          bst2(rU, 0.5f * (ar + br), 0.5f * (ai - bi), (y1 * C::NHP + lane) * 8, C::G * i * 8);
+          const float ai = pl[l], bi = pl[m];
+          bst2(rU, 0.5f * (ar[i] + br[i]), 0.5f * (ai - bi), (y1 * C::NHP + lane) * 8,
+               C::G * i * 8);
           if (has2)
-            bst2(rU, 0.5f * (ai + bi), 0.5f * (br - ar), (y2 * C::NHP + lane) * 8, C::G * i * 8);
+            bst2(rU, 0.5f * (ai + bi), 0.5f * (br[i] - ar[i]), (y2 * C::NHP + lane) * 8,
+                 C::G * i * 8);
         }
       }
     }
@@ -1004,20 +1100,31 @@ k_row_bfwd(RowBwdFwdArgs p) {
   }
 }
 
+// e^(i pi G q / N) for q < NI, evaluated at compile time
+template <int N, int G, int NI>
+struct HalfTurns {
+  float c[NI], s[NI];
+  constexpr HalfTurns() : c(), s() {
+    for (int q = 0; q < NI; ++q) {
+      c[q] = float(detail::cs2pi(long(G) * q, 2L * N, 0));
+      s[q] = float(detail::cs2pi(long(G) * q, 2L * N, 1));
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------------------
 // Backward row pass 2: apply -D_x as its symbol, -D_y from the column pass (low columns) or
 // as a row difference (other columns), and one complex C2R per row for (dgx, dgy).
 // NBO: output blocks j1 that can hold x < W (N1, or kInvHalf<N1> when 2 W <= N)
+// One LDS plane per slot (the real parts of each exchange, then the imaginary parts).
 template <int N1, int N2, int SLOTS, int NBO = N1>
 __global__ void __launch_bounds__((SLOTS * RowCfg<N1, N2>::G))
-k_row_binv(RowBwdInvArgs p) {
+__attribute__((amdgpu_waves_per_eu(3))) k_row_binv(RowBwdInvArgs p) {
   using C = RowCfg<N1, N2>;
-  __shared__ float s_re[SLOTS][C::LDSC];
-  __shared__ float s_im[SLOTS][C::LDSC];
+  __shared__ float s_pl[SLOTS][C::LDSC];
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
-  float* re = s_re[slot];
-  float* im = s_im[slot];
+  float* pl = s_pl[slot];
   int bx, b;
   xcd_contiguous(bx, b);
   // one row per slot: carrying row y + 1 into the next row's iteration costs more
@@ -1031,7 +1138,6 @@ k_row_binv(RowBwdInvArgs p) {
   const rsrc_t rgx = make_buf(p.dgx + b * p.img_out, p.img_out * 4);
   const rsrc_t rgy = make_buf(p.dgy + b * p.img_out, p.img_out * 4);
   const rsrc_t rtw = make_buf(p.twB, (long long)C::N * 8);
-  const rsrc_t rsxm = make_buf(p.sxm, (long long)C::NH * 8);
   const int tz = fresh_zero();
 
   // All loads first (branch-free: rows outside the image read 0 through an out-of-range
@@ -1039,15 +1145,13 @@ k_row_binv(RowBwdInvArgs p) {
   constexpr int NID = (kLowBinsB + C::G) / C::G;  // slices that can hold a bin l <= Kb
   const int ow0 = row_ok ? (y * C::NHP + lane) * 8 : kOOB;
   const int ow1 = row_ok ? ((y + 1) * C::NHP + lane) * 8 : kOOB;
-  cx cur[C::NI], nxt[C::NI], smv[C::NI], sdv[NID];
+  cx cur[C::NI], nxt[C::NI], sdv[NID];
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) {
     const f2b v0 = bld2(rW, ow0, C::G * i * 8);
     const f2b v1 = bld2(rW, ow1, C::G * i * 8);
-    const f2b sm = bld2(rsxm, lane * 8, tz + C::G * i * 8);
     cur[i] = {v0.x, v0.y};
     nxt[i] = {v1.x, v1.y};
-    smv[i] = {sm.x, sm.y};
   }
 #pragma unroll
   for (int i = 0; i < NID; ++i) {
@@ -1055,30 +1159,24 @@ k_row_binv(RowBwdInvArgs p) {
     const f2b v = bld2(rSD, (row_ok && l <= p.Kb) ? (y * Kb1 + l) * 8 : kOOB, 0);
     sdv[i] = {v.x, v.y};
   }
+  // -D_x's symbol 1 - w_N^-l = 2 s (s - i c) with (c, s) = e^(i pi l / N), formed from the
+  // lane's half-angle and a compile-time step per block of G bins: no cancellation at low l
+  float hs, hc;
+  sincospif(float(lane) / float(C::N), &hs, &hc);
+  constexpr HalfTurns<C::N, C::G, C::NI> ht{};
+  // the packed spectrum of dgx + i dgy: X1 = -D_x's part, X2 = -D_y's part
+  cx X1[C::NI], X2[C::NI];
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) {
     const int l = lane + C::G * i;
-    const cx X1 = cmul(smv[i], cur[i]);
-    const cx X2 = (i < NID && l <= p.Kb) ? sdv[i < NID ? i : 0] : csub(cur[i], nxt[i]);
-    if (l < C::NH) {
-      // full spectrum of dgx + i dgy at bins l and N - l
-      re[l] = X1.x - X2.y;
-      im[l] = X1.y + X2.x;
-      if (l != 0 && 2 * l != C::N) {
-        re[C::N - l] = X1.x + X2.y;
-        im[C::N - l] = X2.x - X1.y;
-      }
-    }
+    const float cl = hc * ht.c[i] - hs * ht.s[i], sl = hs * ht.c[i] + hc * ht.s[i];
+    X1[i] = cmul(cx{2.f * sl * sl, -2.f * sl * cl}, cur[i]);
+    X2[i] = (i < NID && l <= p.Kb) ? sdv[i < NID ? i : 0] : csub(cur[i], nxt[i]);
   }
-  slot_sync();
   cx bz[N2];
-  if (lane < N1) {
-#pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) bz[k2] = {re[lane + N1 * k2], im[lane + N1 * k2]};
-  }
-  slot_sync();
+  packed_to_bz<N1, N2>(X1, X2, bz, pl, lane);
   cx a[N1];
-  inv_fft_from_regs<N1, N2>(bz, a, re, im, lane, rtw, tz);
+  inv_fft_from_regs_1p<N1, N2>(bz, a, pl, lane, rtw, tz);
   if constexpr (SLOTS == 1) {
     // uniform row: descriptors whose range is that row, so stores at x >= W (and of a row
     // outside the image) are dropped with no branch; blocks j1 >= NBO are not stored
@@ -1118,7 +1216,7 @@ struct RowLaunch {
   // N1/2 + 1 of them
   static constexpr int NB_HALF = N1 / 2 + 1 < N1 ? N1 / 2 + 1 : N1;
   static hipError_t fwd(const RowFwdArgs& a, int B, hipStream_t s) {
-    const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
+    const int slots_needed = a.npairs;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
     const bool half = 2 * a.W <= N1 * N2;
     const dim3 blk(SLOTS * C::G);
@@ -1153,7 +1251,7 @@ struct RowLaunch {
     }
   }
   static hipError_t inv(const RowInvArgs& a, int B, hipStream_t s) {
-    const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
+    const int slots_needed = a.npairs;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
     const bool half = 2 * a.W <= N1 * N2;
     if (a.mom)
@@ -1166,7 +1264,7 @@ struct RowLaunch {
     return hipGetLastError();
   }
   static hipError_t bfwd(const RowBwdFwdArgs& a, int B, hipStream_t s) {
-    const int slots_needed = (a.npairs + a.ppw - 1) / a.ppw;
+    const int slots_needed = a.npairs;
     dim3 grid((slots_needed + SLOTS - 1) / SLOTS, B);
     if (2 * a.W <= N1 * N2)
       hipLaunchKernelGGL((k_row_bfwd<N1, N2, SLOTS, kInvHalf<N1>>), grid, dim3(SLOTS * C::G), 0,

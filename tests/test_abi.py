@@ -124,8 +124,7 @@ def test_plan_parameters_round_trip_and_low_bins():
     """Launch parameters are set and read back on the host; out-of-range values and unknown
     names are rejected; Kb is a read-only value of the plan; K defaults by the torus shape
     (the smallest of 4, 8, 16, 32 with N <= 16 K M) and may be raised up to 32."""
-    want = {"row_fppw": 2, "row_ppw": 4, "col_c": 8, "col_rows": 32, "col_rows_b": 16,
-            "low_bins": 4}
+    want = {"col_c": 8, "col_rows": 32, "col_rows_b": 16, "low_bins": 4}
     p = gfc.Plan(801, 1200, params=want, tuned=False)
     got = p.params
     assert got.pop("row_split") == p.get_param("row_split_fwd")
@@ -141,7 +140,7 @@ def test_plan_parameters_round_trip_and_low_bins():
         assert (n1, 2400 // n1) in cands, (ps, n1)
     assert gfc.lib().gfc_plan_set_param(p.handle, b"row_split", 7) == 1
     L = gfc.lib()
-    for name, value in (("row_fppw", 0), ("row_fppw", 65), ("col_c", 3), ("col_rows", 24),
+    for name, value in (("row_ppw", 1), ("col_c", 0), ("col_c", 3), ("col_rows", 24),
                         ("col_rows_b", 8), ("low_bins", 3), ("low_bins", 33),
                         ("low_bins_b", 8), ("row_strip", 4)):
         assert L.gfc_plan_set_param(p.handle, name.encode(), value) == 1, (name, value)
