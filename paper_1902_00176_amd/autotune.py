@@ -54,6 +54,7 @@ def time_stages(plan, B, reps=7, torch=None):
     dev = torch.device("cuda:0")
     H, W = plan.H, plan.W
     g = torch.randn((B, H, W), device=dev) * 0.1
+    g2 = torch.randn((B, H, W), device=dev) * 0.1  # gy: its own buffer, as in a real solve
     u = torch.empty_like(g)
     d2 = torch.empty_like(g)
     ws = torch.empty(plan.workspace_size(B), dtype=torch.uint8, device=dev)
@@ -63,7 +64,7 @@ def time_stages(plan, B, reps=7, torch=None):
     h = plan.handle
 
     def f(k):
-        r = L.gfc_solve_batch_stage(h, k, g.data_ptr(), g.data_ptr(), u.data_ptr(), B,
+        r = L.gfc_solve_batch_stage(h, k, g.data_ptr(), g2.data_ptr(), u.data_ptr(), B,
                                     ws.data_ptr(), ws.numel(), sp)
         if r:
             raise gfc.GFCError(r, "gfc_solve_batch_stage")

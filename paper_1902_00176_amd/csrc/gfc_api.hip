@@ -608,7 +608,9 @@ gfc_status gfc_solve_backward_stage(gfc_plan_t p, int stage, const float* du, fl
     c.img_t = img_t;
     c.img_sd = img_sd;
     c.nimg = B;
-    const gfc_status st = hip_status(launch_col_bwd(c, B, s));
+    std::lock_guard<std::mutex> fork_lock(p->fork_mtx);
+    const gfc_status st =
+        hip_status(launch_col_bwd(c, B, s, p->side, p->ev_fork, p->ev_join));
     if (st != GFC_OK) return st;
   }
   if (stage == 0 || stage == 3) {

@@ -110,7 +110,7 @@ __device__ __forceinline__ dc head_moment(const dc* U, int C, int c, int last, i
 // Columns l <= K arrive split: T holds a = (1 - w_N^l) Ex^ and SB holds b = Ey^, and the
 // column input is a + (1 - S) b. The difference is folded into the causal recursion:
 // (1 - rho S)^-1 (1 - S) b = b - (1 - rho) S (1 - rho S)^-1 b, which has no cancellation.
-template <int LMAX, bool LOWTILE, bool TAIL>
+template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int b, dc* E,
                                              dc* U) {
   const int C = p.C;
@@ -140,7 +140,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   // ---- 1. load the segment, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
-  for (int j = 0; j < LMAX; ++j) v[j] = bld2<kNT>(rT, vX + j * rowT, 0);
+  for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rT, vX + j * rowT, 0);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (LOWTILE && low) {
     const rsrc_t rS = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
@@ -256,7 +256,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
         pin(v[j]);
         const double y = double(p0 + j);
         const double val = (D.x + double(v[j].x) - bbar * y) * outs;
-        bst2<kNT>(rT, float(val), 0.f, vS3 + j * rowT, 0);
+        bst2<CP>(rT, float(val), 0.f, vS3 + j * rowT, 0);
       }
     } else {
       const int kseg = kp->kseg;
@@ -278,7 +278,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
         const dc w = dfma(pj, D, dc{v[j].x, v[j].y});
         if (TAIL) z = dsel(j < Ls, dfma(rho, z, w), z);
         else z = dfma(rho, z, w);
-        bst2<kNT>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
+        bst2<CP>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
         pj *= inv_rho;
       }
     }
@@ -293,10 +293,10 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   }
 }
 
-template <int LMAX, bool LOWTILE, bool TAIL>
+template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __global__ void __launch_bounds__(kColMaxThreads) k_col_fwd(ColFwdArgs p) {
   extern __shared__ dc s_mem[];
-  col_fwd_tile<LMAX, LOWTILE, TAIL>(p, p.tile0 + blockIdx.x, blockIdx.y, s_mem,
+  col_fwd_tile<LMAX, LOWTILE, TAIL, CP>(p, p.tile0 + blockIdx.x, blockIdx.y, s_mem,
                                     s_mem + p.nseg * p.C);
 }
 
@@ -314,14 +314,14 @@ k_col_fwd_rg(const RgBase* basep, const RgCol* tab, const RgItem* items) {
   p.T = reinterpret_cast<f2*>(base.ws + e.t);
   p.SB = reinterpret_cast<const f2*>(base.ws + e.side);
   p.partial = reinterpret_cast<double*>(base.ws + e.red);
-  col_fwd_tile<LMAX, LOWTILE, TAIL>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+  col_fwd_tile<LMAX, LOWTILE, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
 }
 
 // ---------------------------------------------------------------------------------------
 // Backward: input rows [0, R), R = H, plus a Dirac of weight dv = -sum(du) w_N^(l c0) at
 // row r0 (the adjoint of the reference-pixel subtraction). Outputs w rows [0, H] and, for
 // l <= Kb, the column derivative (-D_y w)[y] = w_in[y] - (1 - rho) z[y+1] scaled like w.
-template <int LMAX, bool TAIL>
+template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int b, dc* E,
                                              dc* U, double* s_misc) {
   const int C = p.C;
@@ -333,8 +333,8 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   const bool active = s < nseg;
   const int l = tile * C + c;
   const bool col_ok = active && l < p.NH;
-  const bool dcol = col_ok && l == 0;
-  const bool low = col_ok && l <= p.Kb;
+  const bool dcol = LOWTILE && col_ok && l == 0;
+  const bool low = LOWTILE && col_ok && l <= p.Kb;
   const int p0 = s * LMAX;
   const int Ls = (TAIL && s == last) ? p.Llast : LMAX;
   const int R = p.H;
@@ -364,7 +364,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   // ---- 1. load, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
-  for (int j = 0; j < LMAX; ++j) v[j] = bld2<kNT>(rIn, vT + j * rowT, 0);
+  for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rIn, vT + j * rowT, 0);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (dcol) {
     // column 0: inclusive prefix sums of x, and the sum of those prefixes over the segment
@@ -467,7 +467,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
         pin(v[j]);
         const double P = D.x + double(v[j].x) - xbar * double(p0 + j + 1);
         bst2(rD, float(-(P - meanP) * outs), 0.f, vD3 + j * rowD, 0);
-        bst2<kNT>(rT, 0.f, 0.f, vS3 + j * rowT, 0);
+        bst2<CP>(rT, 0.f, 0.f, vS3 + j * rowT, 0);
       }
       if (s == last) bst2(rT, 0.f, 0.f, vEnd, 0);
     } else {
@@ -490,63 +490,70 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
         }
         if (TAIL) z = dsel(j < Ls, dfma(rho, z, w), z);
         else z = dfma(rho, z, w);
-        bst2<kNT>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
+        bst2<CP>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
         pj *= inv_rho;
       }
     }
   }
 }
 
-template <int LMAX, bool TAIL>
+// LOWTILE: the launch of the tiles holding columns l <= Kb (the -D_y output and column 0's
+// pseudo-inverse); the other tiles are compiled without those paths
+template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __global__ void __launch_bounds__(kColMaxThreads) k_col_bwd(ColBwdArgs p) {
   extern __shared__ dc s_mem[];
   dc* E = s_mem;
   dc* U = s_mem + p.nseg * p.C;
   double* s_misc = reinterpret_cast<double*>(s_mem + 2 * p.nseg * p.C);
-  // tiles holding columns l <= Kb (long carry sums) are dispatched first, for every image
-  const int ntiles = (p.NH + p.C - 1) / p.C;
-  const int nlow = min(ntiles, (p.Kb + p.C) / p.C);
-  const int i = blockIdx.x;
-  int tile, b;
-  if (i < nlow * p.nimg) {
-    tile = i % nlow;
-    b = i / nlow;
-  } else {
-    const int j = i - nlow * p.nimg, nr = ntiles - nlow;
-    tile = nlow + j % nr;
-    b = j / nr;
-  }
-  col_bwd_tile<LMAX, TAIL>(p, tile, b, E, U, s_misc);
+  col_bwd_tile<LMAX, LOWTILE, TAIL, CP>(p, p.tile0 + blockIdx.x, blockIdx.y, E, U, s_misc);
 }
 
 namespace {
 // whole waves, so the wave-0 butterflies never read a lane that does not exist
 int col_block(int C, int nseg) { return (C * nseg + 63) / 64 * 64; }
 
+// split: the low tiles on s_low, the others on s; else one launch of the general kernel
 template <int LMAX, bool TAIL>
 void launch_fwd_tiles(const ColFwdArgs& a, int ntiles, int nlow, int B, size_t shm,
-                      hipStream_t s, hipStream_t s_low) {
+                      hipStream_t s, hipStream_t s_low, bool nt, bool split) {
   const dim3 blk(col_block(a.C, a.nseg));
   ColFwdArgs x = a;
+  if (!split) {
+    x.tile0 = 0;
+    hipLaunchKernelGGL((k_col_fwd<LMAX, true, TAIL, 0>), dim3(ntiles, B), blk, shm, s, x);
+    return;
+  }
   if (nlow > 0) {
     x.tile0 = 0;
-    hipLaunchKernelGGL((k_col_fwd<LMAX, true, TAIL>), dim3(nlow, B), blk, shm, s_low, x);
+    hipLaunchKernelGGL((k_col_fwd<LMAX, true, TAIL, 0>), dim3(nlow, B), blk, shm, s_low, x);
   }
   if (ntiles > nlow) {
     x.tile0 = nlow;
-    hipLaunchKernelGGL((k_col_fwd<LMAX, false, TAIL>), dim3(ntiles - nlow, B), blk, shm, s, x);
+    if (nt)
+      hipLaunchKernelGGL((k_col_fwd<LMAX, false, TAIL, kNT>), dim3(ntiles - nlow, B), blk, shm,
+                         s, x);
+    else
+      hipLaunchKernelGGL((k_col_fwd<LMAX, false, TAIL, 0>), dim3(ntiles - nlow, B), blk, shm,
+                         s, x);
   }
 }
 }  // namespace
 
-// Tiles that hold columns l <= K are launched separately so the split-input path costs
-// no registers in the others. Given a side stream and two events, the few low tiles run
-// there, beside the other tiles, and `s` waits for them: they are a small, latency-bound
+// Given a side stream and two events, the tiles that hold columns l <= K are launched
+// separately, on the side stream, beside the other tiles (compiled without the split-input
+// path, which costs registers), and `s` waits for them: they are a small, latency-bound
 // launch that would otherwise run alone. The fork and join cost about 30 us of latency, so
-// batches whose spectra are small (under kSideMinBytes) launch everything on `s`: that
-// halved the column pass of a 64x64 solve and took 5 % off a 48-image 256x256 batch, while
-// 512x512 x 96 and 801x1200 x 100 keep the side stream (2-3 % faster with it).
+// batches whose spectra are small (under kSideMinBytes) launch all tiles at once on `s`
+// with the general kernel: that halved the column pass of a 64x64 solve and took 5 % off a
+// 48-image 256x256 batch, while 512x512 x 96 and 801x1200 x 100 keep the side stream (2-3 %
+// faster with it).
 constexpr long long kSideMinBytes = 100LL << 20;
+// The main tiles read and write the spectra with nontemporal accesses when the batch's
+// spectra exceed the 256 MB memory-side cache by far (801x1200 x 100: 770 MB): the next
+// pass then reads them faster (the forward inverse row pass 0.289 -> 0.270 ms at the time).
+// Smaller batches keep them cached between passes (a 48-image 256x256 batch, 28 MB, and
+// 128^3 volumes, 272 MB, were 6-7 % slower with nontemporal column passes).
+constexpr long long kNtMinBytes = 512LL << 20;
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t side,
                           hipEvent_t fork, hipEvent_t join) {
   const size_t shm = size_t(2 * a.nseg * a.C) * sizeof(dc);
@@ -555,6 +562,7 @@ hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t
   const bool tail = a.Rp != a.nseg * a.Lseg;
   const bool split = side && fork && join && nlow > 0 && ntiles > nlow &&
                      (long long)B * a.img_t * 8 >= kSideMinBytes;
+  const bool nt = (long long)B * a.img_t * 8 >= kNtMinBytes;
   hipStream_t s_low = s;
   if (split) {
     hipError_t e = hipEventRecord(fork, s);
@@ -563,11 +571,11 @@ hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t
     s_low = side;
   }
   if (a.Lseg == 16) {
-    if (tail) launch_fwd_tiles<16, true>(a, ntiles, nlow, B, shm, s, s_low);
-    else launch_fwd_tiles<16, false>(a, ntiles, nlow, B, shm, s, s_low);
+    if (tail) launch_fwd_tiles<16, true>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
+    else launch_fwd_tiles<16, false>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
   } else if (a.Lseg == 32) {
-    if (tail) launch_fwd_tiles<32, true>(a, ntiles, nlow, B, shm, s, s_low);
-    else launch_fwd_tiles<32, false>(a, ntiles, nlow, B, shm, s, s_low);
+    if (tail) launch_fwd_tiles<32, true>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
+    else launch_fwd_tiles<32, false>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
   } else {
     return hipErrorInvalidValue;
   }
@@ -608,22 +616,68 @@ hipError_t launch_col_fwd_rg(const RgBase* base, const RgCol* tab, const RgItem*
   return hipGetLastError();
 }
 
-hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s) {
+namespace {
+// split: the low tiles on s_low, the others on s; else one launch of the general kernel
+template <int LMAX, bool TAIL>
+void launch_bwd_tiles(const ColBwdArgs& a, int ntiles, int nlow, int B, size_t shm,
+                      hipStream_t s, hipStream_t s_low, bool nt, bool split) {
+  const dim3 blk(col_block(a.C, a.nseg));
+  ColBwdArgs x = a;
+  if (!split) {
+    x.tile0 = 0;
+    hipLaunchKernelGGL((k_col_bwd<LMAX, true, TAIL, 0>), dim3(ntiles, B), blk, shm, s, x);
+    return;
+  }
+  if (nlow > 0) {
+    x.tile0 = 0;
+    hipLaunchKernelGGL((k_col_bwd<LMAX, true, TAIL, 0>), dim3(nlow, B), blk, shm, s_low, x);
+  }
+  if (ntiles > nlow) {
+    x.tile0 = nlow;
+    if (nt)
+      hipLaunchKernelGGL((k_col_bwd<LMAX, false, TAIL, kNT>), dim3(ntiles - nlow, B), blk, shm,
+                         s, x);
+    else
+      hipLaunchKernelGGL((k_col_bwd<LMAX, false, TAIL, 0>), dim3(ntiles - nlow, B), blk, shm,
+                         s, x);
+  }
+}
+}  // namespace
+
+// As in the forward pass, the tiles with columns l <= Kb are a launch of their own, on the
+// side stream when one is given and the batch is large, beside the other tiles.
+hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s, hipStream_t side,
+                          hipEvent_t fork, hipEvent_t join) {
   const size_t shm = size_t(2 * a.nseg * a.C) * sizeof(dc) + 8 * sizeof(double);
-  // one-dimensional grid: k_col_bwd maps its index to (tile, image), low tiles first
-  const dim3 grid(((a.NH + a.C - 1) / a.C) * B), blk(col_block(a.C, a.nseg));
   if (a.nimg != B) return hipErrorInvalidValue;
+  const int ntiles = (a.NH + a.C - 1) / a.C;
+  const int nlow = std::min(ntiles, (a.Kb + a.C) / a.C);
   const bool tail = a.Rp != a.nseg * a.Lseg;
+  const bool split = side && fork && join && nlow > 0 && ntiles > nlow &&
+                     (long long)B * a.img_t * 8 >= kSideMinBytes;
+  const bool nt = (long long)B * a.img_t * 8 >= kNtMinBytes;
+  hipStream_t s_low = s;
+  if (split) {
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+    s_low = side;
+  }
   if (a.Lseg == 16) {
-    if (tail) hipLaunchKernelGGL((k_col_bwd<16, true>), grid, blk, shm, s, a);
-    else hipLaunchKernelGGL((k_col_bwd<16, false>), grid, blk, shm, s, a);
+    if (tail) launch_bwd_tiles<16, true>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
+    else launch_bwd_tiles<16, false>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
   } else if (a.Lseg == 32) {
-    if (tail) hipLaunchKernelGGL((k_col_bwd<32, true>), grid, blk, shm, s, a);
-    else hipLaunchKernelGGL((k_col_bwd<32, false>), grid, blk, shm, s, a);
+    if (tail) launch_bwd_tiles<32, true>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
+    else launch_bwd_tiles<32, false>(a, ntiles, nlow, B, shm, s, s_low, nt, split);
   } else {
     return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (split && e == hipSuccess) {
+    e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+  }
+  return e;
 }
 
 }  // namespace gfc

@@ -179,6 +179,7 @@ struct ColBwdArgs {
   int C, nseg, Lseg, Llast, Rp;   // R = H rows of input
   long long img_t, img_sd;
   int nimg;           // images of the launch (B)
+  int tile0;          // first tile of this launch (set by the launcher)
 };
 
 // ---- ragged batches ---------------------------------------------------------------------
@@ -268,7 +269,8 @@ const RowKernels* row_kernel_at(int i);
 
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t side = nullptr,
                           hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
-hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s);
+hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s, hipStream_t side = nullptr,
+                          hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 // ragged forward column pass: items of tiles holding columns l <= K and of the others,
 // one workgroup shape (threads, LDS bytes) for all images, rows per segment Lseg
 hipError_t launch_col_fwd_rg(const RgBase* base, const RgCol* tab, const RgItem* low,
