@@ -317,6 +317,26 @@ k_col_fwd_rg(const RgBase* basep, const RgCol* tab, const RgItem* items) {
   col_fwd_tile<LMAX, LOWTILE, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
 }
 
+// The same over the low-column items followed by the other items in one launch: the first
+// nlow workgroups take the split-input path (a workgroup-uniform branch), so within one
+// stream the long low-column carries run beside the other tiles instead of before them.
+template <int LMAX, bool TAIL>
+__global__ void __launch_bounds__(kColMaxThreads)
+k_col_fwd_rg_all(const RgBase* basep, const RgCol* tab, const RgItem* items, int nlow) {
+  const RgBase base = *basep;  // written by launch_set_base on this stream
+  extern __shared__ dc s_mem[];
+  const RgItem it = items[blockIdx.x];
+  const RgCol& e = tab[it.img];
+  ColFwdArgs p = e.a;
+  p.T = reinterpret_cast<f2*>(base.ws + e.t);
+  p.SB = reinterpret_cast<const f2*>(base.ws + e.side);
+  p.partial = reinterpret_cast<double*>(base.ws + e.red);
+  if (int(blockIdx.x) < nlow)
+    col_fwd_tile<LMAX, true, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+  else
+    col_fwd_tile<LMAX, false, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+}
+
 // ---------------------------------------------------------------------------------------
 // Backward: input rows [0, R), R = H, plus a Dirac of weight dv = -sum(du) w_N^(l c0) at
 // row r0 (the adjoint of the reference-pixel subtraction). Outputs w rows [0, H] and, for
@@ -591,6 +611,11 @@ namespace {
 template <int LMAX, bool TAIL>
 void launch_rg_tiles(const RgBase* base, const RgCol* tab, const RgItem* low, int nlow,
                      const RgItem* rest, int nrest, int threads, size_t shm, hipStream_t s) {
+  if (nlow > 0 && nrest > 0 && rest == low + nlow) {
+    hipLaunchKernelGGL((k_col_fwd_rg_all<LMAX, TAIL>), dim3(nlow + nrest), dim3(threads), shm,
+                       s, base, tab, low, nlow);
+    return;
+  }
   if (nlow > 0)
     hipLaunchKernelGGL((k_col_fwd_rg<LMAX, true, TAIL>), dim3(nlow), dim3(threads), shm, s,
                        base, tab, low);
