@@ -43,34 +43,39 @@ __device__ __forceinline__ dc dsel(bool c, dc a, dc b) { return {c ? a.x : b.x, 
 // keeps the compiler from converting all register-held values to float64 at once
 __device__ __forceinline__ void pin(f2b& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 
-constexpr int kHorner = 8;  // LDS entries loaded together in the carry sums
+// LDS entries loaded together in the carry sums (HC below): the forward pass takes 8; the
+// backward pass, which holds more state beside its segment, takes 4 (with 8 it spilled 8
+// registers and ran 3 % slower; the forward pass ran 2 % slower with 4)
+constexpr int kHornerFwd = 8, kHornerBwd = 4;
 
 // acc <- sum_{t in [t0, t1)} r^(t1-1-t) A[t*C + c] (Horner from t0 upwards); the loads of a
 // chunk are issued together so the chain waits on LDS once per chunk, not per entry
+template <int HC>
 __device__ __forceinline__ dc horner_up(const dc* A, int C, int c, int t0, int t1, double r,
                                         dc acc) {
   int t = t0;
-  for (; t + kHorner <= t1; t += kHorner) {
-    dc e[kHorner];
+  for (; t + HC <= t1; t += HC) {
+    dc e[HC];
 #pragma unroll
-    for (int q = 0; q < kHorner; ++q) e[q] = A[(t + q) * C + c];
+    for (int q = 0; q < HC; ++q) e[q] = A[(t + q) * C + c];
 #pragma unroll
-    for (int q = 0; q < kHorner; ++q) acc = dfma(r, acc, e[q]);
+    for (int q = 0; q < HC; ++q) acc = dfma(r, acc, e[q]);
   }
   for (; t < t1; ++t) acc = dfma(r, acc, A[t * C + c]);
   return acc;
 }
 
 // acc <- sum_{t in (t0, t1]} r^(t-t0-1) A[t*C + c] + r^(t1-t0) acc (Horner from t1 down)
+template <int HC>
 __device__ __forceinline__ dc horner_down(const dc* A, int C, int c, int t1, int t0, double r,
                                           dc acc) {
   int t = t1;
-  for (; t - kHorner >= t0; t -= kHorner) {
-    dc e[kHorner];
+  for (; t - HC >= t0; t -= HC) {
+    dc e[HC];
 #pragma unroll
-    for (int q = 0; q < kHorner; ++q) e[q] = A[(t - q) * C + c];
+    for (int q = 0; q < HC; ++q) e[q] = A[(t - q) * C + c];
 #pragma unroll
-    for (int q = 0; q < kHorner; ++q) acc = dfma(r, acc, e[q]);
+    for (int q = 0; q < HC; ++q) acc = dfma(r, acc, e[q]);
   }
   for (; t > t0; --t) acc = dfma(r, acc, A[t * C + c]);
   return acc;
@@ -79,30 +84,33 @@ __device__ __forceinline__ dc horner_down(const dc* A, int C, int c, int t1, int
 // Carry into segment s from the segments before it: sum over t < s of
 // rho^(Lseg (s-1-t)) e_t (every segment before the last is Lseg rows), over at most kseg
 // segments. rp returns rho^(Lseg s) when the sum is exact (s <= kseg), else 0.
+template <int HC>
 __device__ __forceinline__ dc carry_in(const dc* E, int C, int c, int s, int kseg, double rhoL,
                                        double& rp) {
   const int t0 = s > kseg ? s - kseg : 0;
   double r = 1.0;
   for (int t = 0; t < s && t <= kseg; ++t) r *= rhoL;
   rp = s > kseg ? 0.0 : r;
-  return horner_up(E, C, c, t0, s, rhoL, dc{0.0, 0.0});
+  return horner_up<HC>(E, C, c, t0, s, rhoL, dc{0.0, 0.0});
 }
 
 // z at the row after segment s (anticausal carry) from the moments zst_t of the later
 // segments and z[Rp] = ZR: Z_s = sum_{t > s} rho^(p_t - p_{s+1}) zst_t + rho^(Rp - p_{s+1}) ZR.
+template <int HC>
 __device__ __forceinline__ dc carry_out(const dc* U, int C, int c, int s, int last, int kseg,
                                         double rhoL, double rhoLl, dc ZR) {
   if (s == last) return ZR;
-  if (s + kseg < last) return horner_down(U, C, c, s + kseg, s, rhoL, dc{0.0, 0.0});
+  if (s + kseg < last) return horner_down<HC>(U, C, c, s + kseg, s, rhoL, dc{0.0, 0.0});
   const dc acc = dfma(rhoLl, ZR, U[last * C + c]);  // z at the start of the last segment
-  return horner_down(U, C, c, last - 1, s, rhoL, acc);
+  return horner_down<HC>(U, C, c, last - 1, s, rhoL, acc);
 }
 
 // sum_t rho^(Lseg t) zst_t over the first kseg + 1 segments
+template <int HC>
 __device__ __forceinline__ dc head_moment(const dc* U, int C, int c, int last, int kseg,
                                           double rhoL) {
   const int tmax = kseg < last ? kseg : last;
-  return horner_down(U, C, c, tmax - 1, -1, rhoL, U[tmax * C + c]);
+  return horner_down<HC>(U, C, c, tmax - 1, -1, rhoL, U[tmax * C + c]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -232,8 +240,8 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
       const int kseg = kp->kseg;
       const double rhoL = kp->rhoL;
       double rp, rl;
-      const dc Cs = carry_in(E, C, c, s, kseg, rhoL, rp);
-      const dc Cl = carry_in(E, C, c, last, kseg, rhoL, rl);
+      const dc Cs = carry_in<kHornerFwd>(E, C, c, s, kseg, rhoL, rp);
+      const dc Cl = carry_in<kHornerFwd>(E, C, c, last, kseg, rhoL, rl);
       const dc cR1 = dfma(kp->rhoLl, Cl, E[last * C + c]);  // c0[Rp-1]
       const dc gam = dscale(cR1, kp->cg);
       D = dfma(rp, gam, dscale(Cs, rho));
@@ -261,9 +269,9 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
     } else {
       const int kseg = kp->kseg;
       const double rhoL = kp->rhoL, rhoLl = kp->rhoLl;
-      const dc Sw = head_moment(U, C, c, last, kseg, rhoL);
+      const dc Sw = head_moment<kHornerFwd>(U, C, c, last, kseg, rhoL);
       const dc ZR = dfma(kp->cT, wR1, dscale(Sw, kp->czR));  // z[Rp]
-      dc z = carry_out(U, C, c, s, last, kseg, rhoL, rhoLl, ZR);
+      dc z = carry_out<kHornerFwd>(U, C, c, s, last, kseg, rhoL, rhoLl, ZR);
       if (s == 0) {
         const dc z0 = dfma(last == 0 ? rhoLl : rhoL, z, U[c]);  // z[0]
         const dc zr0 = dfma(kp->ra, wR1, dscale(z0, kp->rb));
@@ -463,8 +471,8 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
       const int kseg = kp->kseg;
       const double rhoL = kp->rhoL;
       double rp, rl;
-      const dc Cs = carry_in(E, C, c, s, kseg, rhoL, rp);
-      const dc Cl = carry_in(E, C, c, last, kseg, rhoL, rl);
+      const dc Cs = carry_in<kHornerBwd>(E, C, c, s, kseg, rhoL, rp);
+      const dc Cl = carry_in<kHornerBwd>(E, C, c, last, kseg, rhoL, rl);
       const dc cR1 = dfma(kp->rhoLl, Cl, E[last * C + c]);
       const dc gam = dfma(kp->cgd, dv, dscale(cR1, kp->cg));
       D = dfma(rp, gam, dscale(Cs, rho));
@@ -493,9 +501,9 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
     } else {
       const int kseg = kp->kseg;
       const double rhoL = kp->rhoL, rhoLl = kp->rhoLl;
-      const dc Sw = head_moment(U, C, c, last, kseg, rhoL);
+      const dc Sw = head_moment<kHornerBwd>(U, C, c, last, kseg, rhoL);
       const dc ZR = dfma(kp->cTd, dv, dfma(kp->cT, wR1, dscale(Sw, kp->czR)));  // z[Rp]
-      dc z = carry_out(U, C, c, s, last, kseg, rhoL, rhoLl, ZR);
+      dc z = carry_out<kHornerBwd>(U, C, c, s, last, kseg, rhoL, rhoLl, ZR);
       if (s == last) bst2(rT, float(z.x * outs), float(z.y * outs), vEnd, 0);
       const double inv_rho = kp->inv_rho;
       const double omr = kp->omr;
