@@ -192,7 +192,12 @@ def main():
             raise SystemExit("--splits times the candidate library: set GFC_LIBRARY to "
                              "paper_1902_00176_amd/_build_tune/libgfc_tune.so")
         lengths = args.lengths or [n for n in range(2, 4097, 2) if gfc.supported_length(n)]
-        db.setdefault("row_splits", {}).update(tune_splits(lengths, torch))
+        rs = db.setdefault("row_splits", {})
+        for n, ent in tune_splits(lengths, torch).items():
+            for keep in ("edit", "edit_ms"):  # hand-measured split of the edit modes
+                if keep in rs.get(n, {}):
+                    ent[keep] = rs[n][keep]
+            rs[n] = ent
     for path in ([db_path] if args.write else []) + ([args.out] if args.out else []):
         with open(path, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)

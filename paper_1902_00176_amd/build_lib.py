@@ -106,7 +106,7 @@ def tuned_splits():
     for n, d in raw.items():
         N = int(n)
         ent = {}
-        for ps in PASSES:
+        for ps in PASSES + ("edit",):
             v = d.get(ps)
             if v and len(v) == 2 and v[0] * v[1] == N and tuple(v) in candidate_splits(N):
                 ent[ps] = (int(v[0]), int(v[1]))
@@ -178,8 +178,11 @@ def generate(lengths, tune=False):
                 entries.append((sym, n))
         else:
             sp = pass_splits(n, tuned)
-            # the forward modes other than the plain solve keep the default split
-            order = [sp["fwd"], choose_factors(n), sp["inv"], sp["bfwd"], sp["binv"]]
+            # the forward modes other than the plain solve (gradient edits, a given Laplacian,
+            # volume slices) take the "edit" split where tuning.json names one (measured by
+            # hand: the autotuner times the plain passes only), else the default split
+            e_sp = tuned.get(n, {}).get("edit", choose_factors(n))
+            order = [sp["fwd"], e_sp, sp["inv"], sp["bfwd"], sp["binv"]]
             args = ", ".join(f"{a}, {b}" for a, b in order)
             sym = f"gfc_row_entry_{n}"
             body = (f"const RowKernels* {sym}() {{\n"
