@@ -845,6 +845,7 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   z.vol_stride = plane * P;
   z.din = D + 1;
   z.dout = P;
+  z.tiled = 1;
   st = hip_status(q->zk->run(z, -1, B, s));
   if (st != GFC_OK) return st;
   ZfftArgs zs = z;
@@ -854,6 +855,7 @@ gfc_status gfc_solve3_batch(gfc_plan3_t q, const float* gx, const float* gy, con
   zs.plane = splane;
   zs.vol_stride = splane * P;
   zs.din = D;
+  zs.tiled = 0;
   zs.T = SB;
   st = hip_status(q->zk->run(zs, -1, B, s));
   if (st != GFC_OK) return st;

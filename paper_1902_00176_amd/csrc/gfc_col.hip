@@ -138,9 +138,13 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   const int Ls = (TAIL && s == last) ? p.Llast : LMAX;
 
   const rsrc_t rT = make_buf(p.T + b * p.img_t, p.img_t * 8);
-  const int rowT = p.NHP * 8;
-  const int vT = col_ok ? (p0 * p.NHP + l) * 8 : kOOB;
+  // tile-major spectra: a thread's rows are 128 bytes apart; rows past the image's H + 1
+  // (the widened last segment) would be the next tile's, so they take out-of-range offsets
+  const int RT = p.H + 1;
+  const int rowT = kTileBins * 8;
+  const int vT = col_ok ? tile_index(p0, l, RT) * 8 : kOOB;
   const int vX = (col_ok && !dcol) ? vT : kOOB;  // column 0 has a = 0
+  const int nin = RT - p0;  // rows of the segment inside the image
 
   const ColConst* kp = p.cc + kz * p.NH + (col_ok ? l : 0);
   const double rho = dcol ? 1.0 : kp->rho;
@@ -148,7 +152,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   // ---- 1. load the segment, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
-  for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rT, vX + j * rowT, 0);
+  for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rT, j < nin ? vX + j * rowT : kOOB, 0);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (LOWTILE && low) {
     const rsrc_t rS = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
@@ -264,7 +268,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
         pin(v[j]);
         const double y = double(p0 + j);
         const double val = (D.x + double(v[j].x) - bbar * y) * outs;
-        bst2<CP>(rT, float(val), 0.f, vS3 + j * rowT, 0);
+        bst2<CP>(rT, float(val), 0.f, j < nin ? vS3 + j * rowT : kOOB, 0);
       }
     } else {
       const int kseg = kp->kseg;
@@ -286,7 +290,7 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
         const dc w = dfma(pj, D, dc{v[j].x, v[j].y});
         if (TAIL) z = dsel(j < Ls, dfma(rho, z, w), z);
         else z = dfma(rho, z, w);
-        bst2<CP>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
+        bst2<CP>(rT, float(z.x * outs), float(z.y * outs), j < nin ? vS3 + j * rowT : kOOB, 0);
         pj *= inv_rho;
       }
     }
@@ -367,13 +371,15 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   const int Ls = (TAIL && s == last) ? p.Llast : LMAX;
   const int R = p.H;
 
-  // loads see the H input rows only (row H of the buffer is an output row)
-  const rsrc_t rIn = make_buf(p.T + b * p.img_t, (long long)R * p.NHP * 8);
+  // tile-major spectra (see the forward pass); loads see the H input rows only (row H of the
+  // buffer is an output row), stores the H + 1 output rows
   const rsrc_t rT = make_buf(p.T + b * p.img_t, p.img_t * 8);
   const rsrc_t rD = make_buf(p.SD + b * p.img_sd, p.img_sd * 8);
-  const int rowT = p.NHP * 8;
+  const int RT = p.H + 1;
+  const int rowT = kTileBins * 8;
+  const int nin = R - p0, nout = RT - p0;  // input and output rows of the segment
   const int rowD = p.KbP * 8;
-  const int vT = col_ok ? (p0 * p.NHP + l) * 8 : kOOB;
+  const int vT = col_ok ? tile_index(p0, l, RT) * 8 : kOOB;
   const int vD = low ? (p0 * p.KbP + l) * 8 : kOOB;
 
   const ColConst* kp = p.cc + (col_ok ? l : 0);
@@ -392,7 +398,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   // ---- 1. load, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
-  for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rIn, vT + j * rowT, 0);
+  for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rT, j < nin ? vT + j * rowT : kOOB, 0);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (dcol) {
     // column 0: inclusive prefix sums of x, and the sum of those prefixes over the segment
@@ -488,14 +494,14 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   asm volatile("" : "+v"(vS3), "+v"(vD3));
   if (col_ok) {
     const double outs = kp->outs;
-    const int vEnd = vS3 + Ls * rowT;  // the row after this segment
+    const int vEnd = Ls < nout ? vS3 + Ls * rowT : kOOB;  // the row after this segment
     if (dcol) {
 #pragma unroll
       for (int j = 0; j < LMAX; ++j) {
         pin(v[j]);
         const double P = D.x + double(v[j].x) - xbar * double(p0 + j + 1);
         bst2(rD, float(-(P - meanP) * outs), 0.f, vD3 + j * rowD, 0);
-        bst2<CP>(rT, 0.f, 0.f, vS3 + j * rowT, 0);
+        bst2<CP>(rT, 0.f, 0.f, j < nout ? vS3 + j * rowT : kOOB, 0);
       }
       if (s == last) bst2(rT, 0.f, 0.f, vEnd, 0);
     } else {
@@ -518,7 +524,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
         }
         if (TAIL) z = dsel(j < Ls, dfma(rho, z, w), z);
         else z = dfma(rho, z, w);
-        bst2<CP>(rT, float(z.x * outs), float(z.y * outs), vS3 + j * rowT, 0);
+        bst2<CP>(rT, float(z.x * outs), float(z.y * outs), j < nout ? vS3 + j * rowT : kOOB, 0);
         pj *= inv_rho;
       }
     }

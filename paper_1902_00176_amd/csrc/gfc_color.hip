@@ -81,7 +81,8 @@ k_sz_combine(f2* T, const f2* SZ, const f2* omz, int H, int NHP, int K, int KP, 
   const int y = i / K1, l = i % K1;
   const f2 o = omz[kz];
   const f2 z = SZ[pl * plane_s + (long long)y * KP + l];
-  f2& t = T[pl * plane_t + (long long)y * NHP + l];
+  f2& t = T[pl * plane_t + tile_index(y, l, H + 1)];  // tile-major planes of H + 1 rows
+  (void)NHP;
   t.x += o.x * z.x - o.y * z.y;
   t.y += o.x * z.y + o.y * z.x;
 }

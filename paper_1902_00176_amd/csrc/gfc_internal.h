@@ -9,6 +9,18 @@ struct f2 {
   float x, y;
 };
 
+// Spectra (T1 and T2 of the forward solve, U and W of the backward one, the planes of a
+// volume) are stored tile-major: within an image (or plane) of R rows and NHP bins per row,
+// bins l come in tiles of 16, and a tile holds its 16 bins of row 0, then of row 1, and so on
+// (complex index tile_index(y, l, R)). The column pass, whose workgroups own one tile of
+// columns, then reads and writes each tile as one contiguous block; a row pass sees a row as
+// 128-byte pieces, one per tile, which cost it nothing measurable against contiguous rows.
+// NHP is a multiple of 32, so every row has whole tiles; an image still takes R * NHP bins.
+constexpr int kTileBins = 16;
+__host__ __device__ __forceinline__ int tile_index(int y, int l, int R) {
+  return ((l >> 4) * R + y) * kTileBins + (l & (kTileBins - 1));
+}
+
 // ---- row passes -----------------------------------------------------------------------
 // Forward row pass: for each row y in [0, H] of the divergence L (block at the torus
 // origin), T1[y, l] = L^[y, l] for l > K, and the split form T1[y, l] = (1 - w_N^l) Ex^[y, l],
@@ -31,17 +43,17 @@ struct RowFwdArgs {
   int edit;           // kEdit*
   float tau2;         // threshold: tau^2 rounded to float32
   float alpha;        // GDM weight in [0, 1]
-  f2* T1;             // [B][H+1][NHP]  (NHP = NH rounded up to 32: row stride)
+  f2* T1;             // [B] images of (H+1) x NHP, tile-major (NHP = NH rounded up to 32)
   f2* SB;             // [B][H][KP]     (KP = side-array row stride >= K + 1)
   const f2* twA;      // [N1][N2]: w_N^(k1 j), forward sign
   const f2* twL;      // [2][kLowBins+1][G]: (1 - w_N^l) w_N^(l j) and w_N^(l j), 0 for j >= N2
   const f2* twX;      // [N + kMaxLowBins + 1]: w_N^m (m < N), then 1 - w_N^l (l <= kMaxLowBins)
   int H, W, K, KP;
-  int N, NHP;         // row length and T1 row stride (used by launch_low_ext)
+  int N, NHP;         // row length and bins per T1 row (used by launch_low_ext)
   int npairs;         // ceil((H+1) / 2)
   long long img_in, img_t1, img_sb;
   // volumes (kIn3D): the launch's image index runs over (volume, z) with z in [0, zd]; gx,
-  // gy, gz are [B][zd][H][W]; T1 planes are [B][zp][H+1][NHP] (plane z of each volume)
+  // gy, gz are [B][zd][H][W]; T1 planes are [B][zp] of (H+1) x NHP (plane z of each volume)
   const float* gz;
   int zd, zp;
   f2* SZ;             // volumes: [B][zp][H][KP] row sums of gz for bins l <= K (plane z < zd)
@@ -59,7 +71,7 @@ struct RowInvArgs {
   int npairs;         // ceil(H / 2)
   long long img_t2, img_u;
   double* mom;        // [B][gridDim.x][2]: sums of u and u^2 per workgroup, or null
-  // volumes: the image index runs over (volume, z), z < zd; T2 planes [B][zp][H+1][NHP],
+  // volumes: the image index runs over (volume, z), z < zd; T2 planes [B][zp] of (H+1) x NHP,
   // partials [B][nparts] per volume (zd = zp = 1 for images)
   int zd, zp;
   int N;              // row length (the ragged launches covering several lengths branch on it)
@@ -79,7 +91,7 @@ struct LapLowArgs {
   const float* L;     // [B][H+1][W+1]
   const double* twD;  // [N][2]: w_N^m = (cos, -sin)(2 pi m / N), float64
   double* Lh;         // [B][H+1][K+1][2]: L^[y, l] (workspace)
-  f2* T1;             // [B][H+1][NHP]
+  f2* T1;             // [B] images of (H+1) x NHP, tile-major
   f2* SB;             // [B][H][KP]
   int H, W, N, K, NHP, KP;
   long long img_L, img_lh, img_t1, img_sb;
@@ -154,7 +166,7 @@ struct ColGeom {
 };
 
 struct ColFwdArgs {
-  f2* T;              // in: T1 [B][H+1][NHP]; out (in place): T2 rows [0, H)
+  f2* T;              // in: T1, [B] tile-major (H+1) x NHP; out (in place): T2 rows [0, H)
   const f2* SB;       // [B][H][KP]
   const ColConst* cc; // [NH]
   double* partial;    // [B][nparts]: per column-tile sums of the reference terms
@@ -169,7 +181,7 @@ struct ColFwdArgs {
 };
 
 struct ColBwdArgs {
-  f2* T;              // in: U [B][H+1][NHP] rows [0, H); out: W rows [0, H]
+  f2* T;              // in: U, [B] tile-major (H+1) x NHP, rows [0, H); out: W rows [0, H]
   f2* SD;             // out: [B][H][KbP]
   const ColConst* cc; // [NH]
   const double* sums; // [B][nsums]: sum(du) = sum of the partials
@@ -213,9 +225,10 @@ struct RgRowInv {
 
 // ---- z transforms of volumes -------------------------------------------------------------
 struct ZfftArgs {
-  f2* T;               // spectra of one volume at T + vol * vol_stride: [P][R][NHP]
+  f2* T;               // spectra of one volume at T + vol * vol_stride: [P] planes of R x NHP
   const f2* tw;        // [P1][P2]: w_P^(k1 j), forward sign
-  int R, NH, NHP;      // rows per plane, row frequencies used, row stride
+  int R, NH, NHP;      // rows per plane, row frequencies used, bins per row
+  int tiled;           // planes tile-major (the spectra T), else row-major (side arrays)
   int din, dout;       // planes read (the rest are zero), planes written
   long long plane, vol_stride;  // elements per plane, per volume
 };

@@ -90,7 +90,7 @@ __device__ __forceinline__ void low_ext_row(const RowFwdArgs& p, int y, int grp)
       float* t1 = reinterpret_cast<float*>(p.T1);
       float* sb = reinterpret_cast<float*>(p.SB);
       if ((lane & 2) == 0)
-        t1[2 * ((long long)y * p.NHP + l) + comp] = sum;
+        t1[2 * (long long)tile_index(y, l, p.H + 1) + comp] = sum;  // tile-major T1
       else if (y < p.H)
         sb[2 * ((long long)y * p.KP + l) + comp] = sum;
     }
@@ -244,9 +244,9 @@ __global__ void __launch_bounds__(64) k_lap_prefix(LapLowArgs a) {
     const double pr = cr + vr, pi = ci + vi;
     if (y < a.H) {
       sb[(long long)y * a.KP + l] = f2{float(pr), float(pi)};
-      t1[(long long)y * a.NHP + l] = f2{0.f, 0.f};
+      t1[tile_index(y, l, a.H + 1)] = f2{0.f, 0.f};  // tile-major T1 of H + 1 rows
     } else if (y == a.H) {
-      t1[(long long)y * a.NHP + l] = f2{float(pr), float(pi)};
+      t1[tile_index(y, l, a.H + 1)] = f2{float(pr), float(pi)};
     }
     cr = __shfl(pr, 63, 64);
     ci = __shfl(pi, 63, 64);

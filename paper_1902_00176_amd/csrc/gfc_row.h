@@ -201,6 +201,22 @@ __device__ __forceinline__ void low_acc_all(cx (&az)[kLowBins + 1], float vz,
 // together.
 constexpr int kOOB = 0x70000000;  // a byte offset past every image (plans keep them < 2^30)
 
+// Byte offsets of the bins lane + G i (i = 0, 1, ...) of row y of a tile-major spectrum image
+// of R rows (lane < G, G a power of two). Each step of i moves G / kTileBins whole tiles (or,
+// for G < kTileBins, part of one), so tile_index's multiply by R is taken once per row and
+// the per-i offsets are a scalar product and an add. A row outside the image (ok false)
+// gets offsets from kOOB up, which stay below 2^32 since an image is below 2^30 bytes.
+template <int G>
+struct RowTiles {
+  unsigned base, tile;  // offset of bin lane (+ tz); bytes per tile of the image
+  __device__ __forceinline__ RowTiles(int y, int lane, int R, bool ok, int tz)
+      : base(ok ? unsigned(tile_index(y, lane, R) * 8 + tz) : unsigned(kOOB)),
+        tile(unsigned(R) * kTileBins * 8) {}
+  __device__ __forceinline__ int operator[](int i) const {
+    return int(base + unsigned(i * G / kTileBins) * tile + unsigned(i * G % kTileBins) * 8);
+  }
+};
+
 // One slot per wavefront: the element x - 1 of lane j is lane j - 1's element x (a DPP
 // shift of the whole wavefront by one lane); lane 0 takes `carry`, the previous y1 block's
 // element of lane N2 - 1. Saves the x - 1 loads of the divergence.
@@ -704,12 +720,15 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
     }
     slot_sync();
     const bool has1 = ok && y0 + 1 <= p.H;
+    const int RT = p.H + 1;  // rows of a T1 image (tile_index)
     if constexpr (SLOTS == 1) {
-      // uniform rows: a descriptor per T1 row with range NH bins (empty outside the image),
-      // so bins l >= NH and missing rows are dropped by the hardware with no branch
+      // uniform rows: a descriptor per T1 row (the image, empty when the row is outside it),
+      // so missing rows are dropped by the hardware with no branch; bins in [NH, NHP) land in
+      // the padding of the last tile, and bins past NHP past the image
       const f2* t1b = p.T1 + tplane * p.img_t1;
-      const rsrc_t w0 = make_buf(t1b + (long long)y0 * C::NHP, ok ? C::NH * 8 : 0);
-      const rsrc_t w1 = make_buf(t1b + (long long)(y0 + 1) * C::NHP, has1 ? C::NH * 8 : 0);
+      const rsrc_t w0 = make_buf(t1b, ok ? p.img_t1 * 8 : 0);
+      const rsrc_t w1 = make_buf(t1b, has1 ? p.img_t1 * 8 : 0);
+      const RowTiles<C::G> rt(y0, lane, RT, true, tz);
 #pragma unroll
       for (int i = 0; i < C::NI; ++i) {
         const int l = lane + C::G * i;
@@ -719,7 +738,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         const float ar = zr[i], ai = pl[inside ? l : 0], br = zm[i], bi = pl[m];
         cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
         cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
-        int off = (lane + C::G * i) * 8 + tz;
+        int off = rt[i];
         if constexpr (!FULLBINS) {
           if (i == 0) {
             // bins 1..K come from the direct sums; bin 0 of T1 is (1 - w_N^0) Ex^ = 0
@@ -728,7 +747,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
           }
         }
         bst2(w0, A.x, A.y, off, 0);
-        bst2(w1, B.x, B.y, off, 0);
+        bst2(w1, B.x, B.y, off + kTileBins * 8, 0);  // row y0 + 1: the next row of the tile
       }
     } else {
 #pragma unroll
@@ -742,8 +761,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
           const float ar = zr[i], ai = pl[l], br = zm[i], bi = pl[m];
           const cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
           const cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
-          bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
-          if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
+          bst2(rT1, A.x, A.y, tile_index(y0, l, RT) * 8, 0);
+          if (has1) bst2(rT1, B.x, B.y, tile_index(y0 + 1, l, RT) * 8, 0);
         }
       } else if (ok && l < C::NH && (l == 0 || l > KL)) {
         const int m = (l == 0) ? 0 : C::N - l;
@@ -751,8 +770,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         cx A = {0.5f * (ar + br), 0.5f * (ai - bi)};
         cx B = {0.5f * (ai + bi), 0.5f * (br - ar)};
         if (l == 0) A = B = {0.f, 0.f};  // (1 - w_N^0) Ex^ = 0; Ey^ goes to SB
-        bst2(rT1, A.x, A.y, (y0 * C::NHP + lane) * 8, C::G * i * 8);
-        if (has1) bst2(rT1, B.x, B.y, ((y0 + 1) * C::NHP + lane) * 8, C::G * i * 8);
+        bst2(rT1, A.x, A.y, tile_index(y0, l, RT) * 8, 0);
+        if (has1) bst2(rT1, B.x, B.y, tile_index(y0 + 1, l, RT) * 8, 0);
       }
     }
     }
@@ -763,7 +782,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
         const int rr = v / (2 * NC), c = (v / 2) % NC, comp = v & 1;
         const int y = y0 + rr;
         if (c < KL) {
-          if (y <= p.H) bst1(rT1, lowsum[k], (y * C::NHP + c + 1) * 8 + comp * 4, 0);
+          if (y <= p.H) bst1(rT1, lowsum[k], tile_index(y, c + 1, RT) * 8 + comp * 4, 0);
         } else if (c < 2 * KL + 1) {
           if (y < p.H) bst1(rSB, lowsum[k], (y * p.KP + c - KL) * 8 + comp * 4, 0);
         } else if (y < p.H) {
@@ -890,19 +909,23 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
     const int y1 = 2 * q, y2 = 2 * q + 1;
     const bool has2 = ok && y2 < p.H;
     cx bz[N2];
+    const int RT = p.H + 1;  // rows of a T2 image (tile_index)
     if constexpr (SLOTS == 1) {
-      // One slot per wavefront: the rows are uniform and each has a descriptor whose range
-      // is that row, empty outside the image. The spectrum bins are read in natural order
-      // (coalesced; bins >= NH and missing rows read 0) and reach the four-step layout
-      // through LDS.
-      const rsrc_t r1 = make_buf(T2i + (long long)y1 * C::NHP, ok ? C::NH * 8 : 0);
-      const rsrc_t r2 = make_buf(T2i + (long long)y2 * C::NHP, has2 ? C::NH * 8 : 0);
+      // One slot per wavefront: the rows are uniform and each has a descriptor for the image,
+      // empty when the row is outside it (its loads read 0). The spectrum bins are read in
+      // natural order (bins in [NH, NHP) read the last tile's padding, unused) and reach the
+      // four-step layout through LDS.
+      const rsrc_t r1 = make_buf(T2i, ok ? p.img_t2 * 8 : 0);
+      const rsrc_t r2 = make_buf(T2i, has2 ? p.img_t2 * 8 : 0);
       cx X1[C::NI], X2[C::NI];
+      const RowTiles<C::G> rt(y1, lane, RT, true, tz);
 #pragma unroll
       for (int i = 0; i < C::NI; ++i) {
-        // the bin in the per-lane offset, so that the range check covers it
-        const f2b v1 = bld2(r1, (lane + C::G * i + tz) * 8, 0);
-        const f2b v2 = bld2(r2, (lane + C::G * i + tz) * 8, 0);
+        // the whole offset per lane, so that the range check covers it (row y2 = y1 + 1 is
+        // the next row of the tile)
+        const int o = rt[i];
+        const f2b v1 = bld2(r1, o, 0);
+        const f2b v2 = bld2(r2, o + kTileBins * 8, 0);
         X1[i] = {v1.x, v1.y};
         X2[i] = {v2.x, v2.y};
       }
@@ -916,8 +939,8 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
         const int kk = lane + N1 * k2;
         const int m = kk < C::NH ? kk : C::N - kk;
         f2b X1 = {0.f, 0.f}, X2 = {0.f, 0.f};
-        if (ok) X1 = bld2(rT2, (y1 * C::NHP + m) * 8, 0);
-        if (has2) X2 = bld2(rT2, (y2 * C::NHP + m) * 8, 0);
+        if (ok) X1 = bld2(rT2, tile_index(y1, m, RT) * 8, 0);
+        if (has2) X2 = bld2(rT2, tile_index(y2, m, RT) * 8, 0);
         if (kk < C::NH) bz[k2] = {X1.x - X2.y, X1.y + X2.x};
         else bz[k2] = {X1.x + X2.y, X2.x - X1.y};
       }
@@ -1072,17 +1095,16 @@ __attribute__((amdgpu_waves_per_eu(3))) k_row_bfwd(RowBwdFwdArgs p) {
     // the DC bin of the packed transform is (sum of row y1) + i (sum of row y2)
     if (lane == 0) lsum += double(ar[0]) + double(pl[0]);
     if (ok) {
+      const RowTiles<C::G> rt(y1, lane, p.H + 1, true, 0);  // U images have H + 1 rows
 #pragma unroll
       for (int i = 0; i < C::NI; ++i) {
         const int l = lane + C::G * i;
         if (l < C::NH) {
           const int m = (l == 0) ? 0 : C::N - l;
           const float ai = pl[l], bi = pl[m];
-          bst2(rU, 0.5f * (ar[i] + br[i]), 0.5f * (ai - bi), (y1 * C::NHP + lane) * 8,
-               C::G * i * 8);
-          if (has2)
-            bst2(rU, 0.5f * (ai + bi), 0.5f * (br[i] - ar[i]), (y2 * C::NHP + lane) * 8,
-                 C::G * i * 8);
+          const int o = rt[i];
+          bst2(rU, 0.5f * (ar[i] + br[i]), 0.5f * (ai - bi), o, 0);
+          if (has2) bst2(rU, 0.5f * (ai + bi), 0.5f * (br[i] - ar[i]), o + kTileBins * 8, 0);
         }
       }
     }
@@ -1143,13 +1165,14 @@ __attribute__((amdgpu_waves_per_eu(3))) k_row_binv(RowBwdInvArgs p) {
   // All loads first (branch-free: rows outside the image read 0 through an out-of-range
   // offset, bins past NH are loaded and ignored), so they are in flight together.
   constexpr int NID = (kLowBinsB + C::G) / C::G;  // slices that can hold a bin l <= Kb
-  const int ow0 = row_ok ? (y * C::NHP + lane) * 8 : kOOB;
-  const int ow1 = row_ok ? ((y + 1) * C::NHP + lane) * 8 : kOOB;
   cx cur[C::NI], nxt[C::NI], sdv[NID];
+  const RowTiles<C::G> rt(y, lane, p.H + 1, row_ok, tz);  // W images have H + 1 rows
 #pragma unroll
   for (int i = 0; i < C::NI; ++i) {
-    const f2b v0 = bld2(rW, ow0, C::G * i * 8);
-    const f2b v1 = bld2(rW, ow1, C::G * i * 8);
+    // row y + 1 is the next row of the tile
+    const int o = rt[i];
+    const f2b v0 = bld2(rW, o, 0);
+    const f2b v1 = bld2(rW, o + kTileBins * 8, 0);
     cur[i] = {v0.x, v0.y};
     nxt[i] = {v1.x, v1.y};
   }

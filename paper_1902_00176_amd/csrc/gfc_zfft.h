@@ -1,8 +1,9 @@
 // gfc_zfft.h - FFTs along z for volumes: the third axis of the n-D solve (eq. (5) holds in
-// any dimension). The spectra of a volume are planes [P][R][NHP] (z, row y, row frequency l);
-// the transform runs over z for every (y, l). A workgroup takes one row y and a tile of TL
-// consecutive l: coalesced loads of TL * 8 bytes per plane into LDS, one four-step FFT of
-// length P = P1 * P2 per slot of G lanes (as the row passes), coalesced stores.
+// any dimension). The spectra of a volume are P planes of R x NHP (z, row y, row frequency l),
+// each tile-major as the images are (side arrays row-major); the transform runs over z for
+// every (y, l). A workgroup takes one row y and TL <= 16 consecutive l, contiguous within
+// a tile: coalesced loads of TL * 8 bytes per plane into LDS, one four-step FFT of length
+// P = P1 * P2 per slot of G lanes (as the row passes), coalesced stores.
 #pragma once
 #include "gfc_buf.h"
 #include "gfc_dft.h"
@@ -46,7 +47,8 @@ k_zfft(ZfftArgs a) {
     const int c = i % TL, z = i / TL;
     const int l = l0 + c;
     const bool in = z < a.din && l < a.NH;
-    const long long e = (long long)z * a.plane + (long long)y * a.NHP + l;
+    const long long e =
+        (long long)z * a.plane + (a.tiled ? tile_index(y, l, a.R) : y * a.NHP + l);
     const f2b v = bld2(rT, in ? int(e * 8) : kZOob, 0);
     s_lds[c][z] = v.x;
     s_lds[c][C::S + z] = v.y;
@@ -99,7 +101,8 @@ k_zfft(ZfftArgs a) {
     const int l = l0 + cc;
     if (l < a.NH)
       bst2(rT, s_lds[cc][z], s_lds[cc][C::S + z],
-           int(((long long)z * a.plane + (long long)y * a.NHP + l) * 8), 0);
+           int(((long long)z * a.plane +
+                (a.tiled ? tile_index(y, l, a.R) : y * a.NHP + l)) * 8), 0);
   }
 }
 

@@ -1,9 +1,11 @@
 """Pass-level GPU checks: the forward row pass, the column pass and the inverse row pass, and
 the first and last backward passes, each alone, through gfc_solve_batch_stage and
 gfc_solve_backward_stage, against float64 numpy transforms of the same inputs. The intermediate
-layout is the library's workspace (spectra T [B][H+1][NHP] complex64 from offset 0; the
-split side array SB [B][H][KP] at the next 256-byte boundary; column partials after it), so
-these tests know that layout on purpose."""
+layout is the library's workspace (spectra T, B images of (H+1) x NHP complex64 from offset 0,
+each stored tile-major: bin l of row y at ((l // 16) * (H+1) + y) * 16 + l % 16, so that a
+column tile's 16 bins run contiguously down the rows; the split side array SB [B][H][KP]
+row-major at the next 256-byte boundary; column partials after it), so these tests know that
+layout on purpose."""
 import ctypes
 import os
 import sys
@@ -58,6 +60,17 @@ def _stage(plan, k, gx, gy, u, B, ws):
     assert r == 0, gfc.lib().gfc_status_str(r)
 
 
+def _from_tiles(flat, B, R, NHP):
+    """Spectra in the workspace's tile-major order -> [B][R][NHP]."""
+    return flat.reshape(B, NHP // 16, R, 16).transpose(0, 2, 1, 3).reshape(B, R, NHP)
+
+
+def _to_tiles(a):
+    """[B][R][NHP] -> the workspace's tile-major order, flat."""
+    B, R, NHP = a.shape
+    return np.ascontiguousarray(a.reshape(B, R, NHP // 16, 16).transpose(0, 2, 1, 3)).reshape(-1)
+
+
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
@@ -83,7 +96,7 @@ def test_forward_row_pass_alone(H, W, M, N, K):
     torch.cuda.synchronize()
     raw = ws.cpu().numpy()
     t_bytes = B * (H + 1) * NHP * 8
-    T = raw[:t_bytes].view(np.complex64).reshape(B, H + 1, NHP)[:, :, :NH].astype(np.complex128)
+    T = _from_tiles(raw[:t_bytes].view(np.complex64), B, H + 1, NHP)[:, :, :NH].astype(np.complex128)
     s0 = _align256(t_bytes)
     SB = raw[s0:s0 + B * H * KP * 8].view(np.complex64).reshape(B, H, KP)[:, :, :K + 1]
     l = np.arange(NH)
@@ -130,7 +143,7 @@ def test_inverse_row_pass_alone(H, W, M, N):
     ws = torch.zeros(plan.workspace_size(B), dtype=torch.uint8, device="cuda")
     raw = np.zeros(ws.numel(), np.uint8)
     t_bytes = B * (H + 1) * NHP * 8
-    raw[:t_bytes] = T2.reshape(-1).view(np.uint8)
+    raw[:t_bytes] = _to_tiles(T2).view(np.uint8)
     side = _align256(t_bytes)
     red = side + _align256(max(B * H * KP * 8, B * H * KbP * 8))
     raw[red:red + part.nbytes] = part.reshape(-1).view(np.uint8)
@@ -180,7 +193,7 @@ def test_column_pass_alone(H, W, M, N):
     SB = SB.astype(np.complex64)
     raw = np.zeros(plan.workspace_size(B), np.uint8)
     t_bytes = B * (H + 1) * NHP * 8
-    raw[:t_bytes] = T1.reshape(-1).view(np.uint8)
+    raw[:t_bytes] = _to_tiles(T1).view(np.uint8)
     side = _align256(t_bytes)
     raw[side:side + SB.nbytes] = SB.reshape(-1).view(np.uint8)
     red = side + _align256(max(B * H * KP * 8, B * H * KbP * 8))
@@ -189,7 +202,7 @@ def test_column_pass_alone(H, W, M, N):
     _stage(plan, 2, dummy, dummy, dummy, B, ws)
     torch.cuda.synchronize()
     out = ws.cpu().numpy()
-    T2 = out[:t_bytes].view(np.complex64).reshape(B, H + 1, NHP)
+    T2 = _from_tiles(out[:t_bytes].view(np.complex64), B, H + 1, NHP)
     part = out[red:red + B * ntiles * 8].view(np.float64).reshape(B, ntiles)
     G = O.green_spectrum(M, N)[:, :NH]
     for b in range(B):
@@ -247,7 +260,7 @@ def test_backward_row_pass_alone(H, W, M, N):
     torch.cuda.synchronize()
     raw = ws.cpu().numpy()
     t_bytes = B * (H + 1) * NHP * 8
-    U = raw[:t_bytes].view(np.complex64).reshape(B, H + 1, NHP)
+    U = _from_tiles(raw[:t_bytes].view(np.complex64), B, H + 1, NHP)
     red = _align256(t_bytes) + _align256(max(B * H * KP * 8, B * H * KbP * 8))
     sums = raw[red:red + (len(raw) - red) // 8 * 8].view(np.float64)
     for b in range(B):
@@ -296,7 +309,7 @@ def test_backward_inverse_row_pass_alone(H, W, M, N):
     SD = SD.astype(np.complex64)
     raw = np.zeros(plan.workspace_size(B), np.uint8)
     t_bytes = B * (H + 1) * NHP * 8
-    raw[:t_bytes] = Wv.reshape(-1).view(np.uint8)
+    raw[:t_bytes] = _to_tiles(Wv).view(np.uint8)
     side = _align256(t_bytes)
     raw[side:side + SD.nbytes] = SD.reshape(-1).view(np.uint8)
     ws = torch.from_numpy(raw).cuda()
