@@ -46,4 +46,23 @@ __device__ __forceinline__ void bst1(rsrc_t r, float x, int voff, int soff) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, CP);
 }
 
+// Lane t's part of a sum of n float64 values (the partial sums one pass leaves for the
+// next): elements t, t + W, t + 2W, ... added in that order. A loop of single loads pays a
+// memory latency per element; here U loads are in flight at a time, and elements past n
+// read 0 through the buffer range (adding +0 changes no sum). Callers combine the lanes'
+// parts in a fixed order.
+template <int W, int U>
+__device__ __forceinline__ double strided_sum(const double* p, int n, int t) {
+  const rsrc_t r = make_buf(p, (long long)n * 8);
+  double s = 0.0;
+  for (int j0 = 0; j0 < n; j0 += U * W) {
+    double v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = __builtin_bit_cast(double, bld2(r, (j0 + t + W * k) * 8, 0));
+#pragma unroll
+    for (int k = 0; k < U; ++k) s += v[k];
+  }
+  return s;
+}
+
 }  // namespace gfc

@@ -388,8 +388,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   // sum(du) from the row pass's partials: wave 0 reduces them (lane-strided sums, then a
   // fixed-order butterfly) and leaves the total in LDS for after the first barrier
   if (threadIdx.x < 64) {
-    double S = 0.0;
-    for (int j = threadIdx.x; j < p.nsums; j += 64) S += p.sums[(long long)b * p.nsums + j];
+    double S = strided_sum<64, 8>(p.sums + (long long)b * p.nsums, p.nsums, threadIdx.x);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) S += __shfl_xor(S, off, 64);
     if (threadIdx.x == 0) s_misc[0] = S;

@@ -19,10 +19,23 @@ k_color_apply(float* u, const double* mom, int nparts, const float* I_mean, cons
   __shared__ double s1[kColorThreads], s2[kColorThreads];
   const int b = blockIdx.y;
   const int t = threadIdx.x;
+  // thread-strided sums of the moment pairs, four pairs in flight at a time (pairs past
+  // nparts read 0), then the LDS tree
+  const rsrc_t rm = make_buf(mom + 2 * (long long)b * nparts, (long long)nparts * 16);
   double a1 = 0.0, a2 = 0.0;
-  for (int j = t; j < nparts; j += kColorThreads) {
-    a1 += mom[2 * ((long long)b * nparts + j)];
-    a2 += mom[2 * ((long long)b * nparts + j) + 1];
+  for (int j0 = 0; j0 < nparts; j0 += 4 * kColorThreads) {
+    double v1[4], v2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int o = (j0 + t + kColorThreads * k) * 16;
+      v1[k] = __builtin_bit_cast(double, bld2(rm, o, 0));
+      v2[k] = __builtin_bit_cast(double, bld2(rm, o + 8, 0));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a1 += v1[k];
+      a2 += v2[k];
+    }
   }
   s1[t] = a1;
   s2[t] = a2;
@@ -104,8 +117,7 @@ k_partial_sums(const double* partial, int nparts, double* total) {
   __shared__ double sh[kScanThreads];
   const int t = threadIdx.x;
   const double* in = partial + (long long)blockIdx.x * nparts;
-  double a = 0.0;
-  for (int j = t; j < nparts; j += kScanThreads) a += in[j];
+  double a = strided_sum<kScanThreads, 4>(in, nparts, t);
   sh[t] = a;
   __syncthreads();
   for (int d = kScanThreads / 2; d > 0; d >>= 1) {

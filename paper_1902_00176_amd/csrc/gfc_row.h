@@ -896,8 +896,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs p, int bx, int b, 
 
   // v_ref = sum of the column pass's per-tile partials: lane-strided sums, then a fixed-order
   // butterfly across the slot (every lane ends with the same, deterministic total)
-  double vr = 0.0;
-  for (int j = lane; j < p.nparts; j += C::G) vr += p.partial[(long long)vol * p.nparts + j];
+  double vr = strided_sum<C::G, 4>(p.partial + (long long)vol * p.nparts, p.nparts, lane);
 #pragma unroll
   for (int off = C::G / 2; off > 0; off >>= 1) vr += __shfl_xor(vr, off, C::G);
   const float vref = float(vr);
