@@ -118,9 +118,35 @@ __device__ __forceinline__ dc head_moment(const dc* U, int C, int c, int last, i
 // Columns l <= K arrive split: T holds a = (1 - w_N^l) Ex^ and SB holds b = Ey^, and the
 // column input is a + (1 - S) b. The difference is folded into the causal recursion:
 // (1 - rho S)^-1 (1 - S) b = b - (1 - rho) S (1 - rho S)^-1 b, which has no cancellation.
+// The recursion constants of columns [l0, l0 + C) into LDS (columns past nh read 0), four
+// words in flight per thread; visible after the caller's next barrier. The passes read
+// them after their barriers, where each read from global memory (an L2 round trip) would
+// stall the workgroup again.
+constexpr int kColMaxC = 64;  // widest column tile (plans keep col_c <= 64)
+__device__ __forceinline__ void stage_consts(ColConst* dst, const ColConst* tab, int l0, int C,
+                                             int nh) {
+  constexpr int kW = int(sizeof(ColConst) / 8);
+  const int nw = C * kW;
+  const int have = (nh - l0 < C ? nh - l0 : C) * kW;
+  const rsrc_t r = make_buf(tab + l0, (long long)(have > 0 ? have : 0) * 8);
+  double* d = reinterpret_cast<double*>(dst);
+  const int nt = int(blockDim.x);
+  for (int w0 = 0; w0 < nw; w0 += 4 * nt) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[k] = __builtin_bit_cast(double, bld2(r, (w0 + int(threadIdx.x) + k * nt) * 8, 0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int w = w0 + int(threadIdx.x) + k * nt;
+      if (w < nw) d[w] = v[k];
+    }
+  }
+}
+
 template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int b, dc* E,
-                                             dc* U) {
+                                             dc* U, ColConst* s_cc) {
   const int C = p.C;
   const int cl = __builtin_ctz(C);
   const int nseg = p.nseg;
@@ -146,19 +172,23 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
   const int vX = (col_ok && !dcol) ? vT : kOOB;  // column 0 has a = 0
   const int nin = RT - p0;  // rows of the segment inside the image
 
-  const ColConst* kp = p.cc + kz * p.NH + (col_ok ? l : 0);
-  const double rho = dcol ? 1.0 : kp->rho;
+  // the causal sweep reads its constants from the table; the later phases from the copy in
+  // LDS that the loads below overlap
+  const ColConst* kg = p.cc + kz * p.NH + (col_ok ? l : 0);
+  const ColConst* kp = s_cc + c;
+  const double rho = dcol ? 1.0 : kg->rho;
 
   // ---- 1. load the segment, causal sweep from a zero state ----
   f2b v[LMAX];
 #pragma unroll
   for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rT, j < nin ? vX + j * rowT : kOOB, 0);
+  stage_consts(s_cc, p.cc + kz * p.NH, tile * C, C, p.NH);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (LOWTILE && low) {
     const rsrc_t rS = make_buf(p.SB + b * p.img_sb, p.img_sb * 8);
     const int rowS = p.KP * 8;
     const int vS = (p0 * p.KP + l) * 8;
-    const double omr = kp->omr;
+    const double omr = kg->omr;
     if (dcol) {
       // column 0: the running sum of b; v gets the exclusive prefix
       dc st = {0.0, 0.0};
@@ -308,8 +338,9 @@ __device__ __forceinline__ void col_fwd_tile(const ColFwdArgs& p, int tile, int 
 template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __global__ void __launch_bounds__(kColMaxThreads) k_col_fwd(ColFwdArgs p) {
   extern __shared__ dc s_mem[];
+  __shared__ ColConst s_cc[kColMaxC];
   col_fwd_tile<LMAX, LOWTILE, TAIL, CP>(p, p.tile0 + blockIdx.x, blockIdx.y, s_mem,
-                                    s_mem + p.nseg * p.C);
+                                    s_mem + p.nseg * p.C, s_cc);
 }
 
 // ragged batches: one (image, tile) work item per workgroup, the image's arguments from a
@@ -326,7 +357,8 @@ k_col_fwd_rg(const RgBase* basep, const RgCol* tab, const RgItem* items) {
   p.T = reinterpret_cast<f2*>(base.ws + e.t);
   p.SB = reinterpret_cast<const f2*>(base.ws + e.side);
   p.partial = reinterpret_cast<double*>(base.ws + e.red);
-  col_fwd_tile<LMAX, LOWTILE, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+  __shared__ ColConst s_cc[kColMaxC];
+  col_fwd_tile<LMAX, LOWTILE, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C, s_cc);
 }
 
 // The same over the low-column items followed by the other items in one launch: the first
@@ -343,10 +375,11 @@ k_col_fwd_rg_all(const RgBase* basep, const RgCol* tab, const RgItem* items, int
   p.T = reinterpret_cast<f2*>(base.ws + e.t);
   p.SB = reinterpret_cast<const f2*>(base.ws + e.side);
   p.partial = reinterpret_cast<double*>(base.ws + e.red);
+  __shared__ ColConst s_cc[kColMaxC];
   if (int(blockIdx.x) < nlow)
-    col_fwd_tile<LMAX, true, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+    col_fwd_tile<LMAX, true, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C, s_cc);
   else
-    col_fwd_tile<LMAX, false, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C);
+    col_fwd_tile<LMAX, false, TAIL, kNT>(p, it.blk, 0, s_mem, s_mem + p.nseg * p.C, s_cc);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -355,7 +388,7 @@ k_col_fwd_rg_all(const RgBase* basep, const RgCol* tab, const RgItem* items, int
 // l <= Kb, the column derivative (-D_y w)[y] = w_in[y] - (1 - rho) z[y+1] scaled like w.
 template <int LMAX, bool LOWTILE, bool TAIL, int CP>
 __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int b, dc* E,
-                                             dc* U, double* s_misc) {
+                                             dc* U, double* s_misc, ColConst* s_cc) {
   const int C = p.C;
   const int cl = __builtin_ctz(C);
   const int nseg = p.nseg;
@@ -382,8 +415,10 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   const int vT = col_ok ? tile_index(p0, l, RT) * 8 : kOOB;
   const int vD = low ? (p0 * p.KbP + l) * 8 : kOOB;
 
-  const ColConst* kp = p.cc + (col_ok ? l : 0);
-  const double rho = dcol ? 1.0 : kp->rho;
+  // the causal sweep reads rho from the table; the later phases their constants from the
+  // copy in LDS that the loads below overlap
+  const ColConst* kp = s_cc + c;
+  const double rho = dcol ? 1.0 : p.cc[col_ok ? l : 0].rho;
 
   // sum(du) from the row pass's partials: wave 0 reduces them (lane-strided sums, then a
   // fixed-order butterfly) and leaves the total in LDS for after the first barrier
@@ -398,6 +433,7 @@ __device__ __forceinline__ void col_bwd_tile(const ColBwdArgs& p, int tile, int 
   f2b v[LMAX];
 #pragma unroll
   for (int j = 0; j < LMAX; ++j) v[j] = bld2<CP>(rT, j < nin ? vT + j * rowT : kOOB, 0);
+  stage_consts(s_cc, p.cc, tile * C, C, p.NH);
   dc e = {0.0, 0.0}, mu = {0.0, 0.0};
   if (dcol) {
     // column 0: inclusive prefix sums of x, and the sum of those prefixes over the segment
@@ -538,7 +574,8 @@ __global__ void __launch_bounds__(kColMaxThreads) k_col_bwd(ColBwdArgs p) {
   dc* E = s_mem;
   dc* U = s_mem + p.nseg * p.C;
   double* s_misc = reinterpret_cast<double*>(s_mem + 2 * p.nseg * p.C);
-  col_bwd_tile<LMAX, LOWTILE, TAIL, CP>(p, p.tile0 + blockIdx.x, blockIdx.y, E, U, s_misc);
+  __shared__ ColConst s_cc[kColMaxC];
+  col_bwd_tile<LMAX, LOWTILE, TAIL, CP>(p, p.tile0 + blockIdx.x, blockIdx.y, E, U, s_misc, s_cc);
 }
 
 namespace {
