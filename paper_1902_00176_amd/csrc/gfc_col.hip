@@ -624,6 +624,11 @@ constexpr long long kSideMinBytes = 100LL << 20;
 // Smaller batches keep them cached between passes (a 48-image 256x256 batch, 28 MB, and
 // 128^3 volumes, 272 MB, were 6-7 % slower with nontemporal column passes).
 constexpr long long kNtMinBytes = 512LL << 20;
+// The backward column pass gains from nontemporal accesses from smaller batches on: the
+// backward inverse row pass after it reads W 12-13 % faster (214-346 MB of spectra:
+// 512x512 x 96, 640x640 x 64, 1024x1024 x 40; backward step 5-8 % faster), where the
+// forward solve changed by under 1 %. The backward pass has no volume form.
+constexpr long long kNtMinBytesBwd = 64LL << 20;
 hipError_t launch_col_fwd(const ColFwdArgs& a, int B, hipStream_t s, hipStream_t side,
                           hipEvent_t fork, hipEvent_t join) {
   const size_t shm = size_t(2 * a.nseg * a.C) * sizeof(dc);
@@ -730,7 +735,7 @@ hipError_t launch_col_bwd(const ColBwdArgs& a, int B, hipStream_t s, hipStream_t
   const bool tail = a.Rp != a.nseg * a.Lseg;
   const bool split = side && fork && join && nlow > 0 && ntiles > nlow &&
                      (long long)B * a.img_t * 8 >= kSideMinBytes;
-  const bool nt = (long long)B * a.img_t * 8 >= kNtMinBytes;
+  const bool nt = (long long)B * a.img_t * 8 >= kNtMinBytesBwd;
   hipStream_t s_low = s;
   if (split) {
     hipError_t e = hipEventRecord(fork, s);
