@@ -1352,8 +1352,16 @@ constexpr int cmax_n(int a) { return a; }
 template <class... T>
 constexpr int cmax_n(int a, int b, T... r) { return cmax_n(cmax(a, b), r...); }
 
+// Groups whose forward entries all have N1 <= 40 are held to three wavefronts per SIMD (168
+// registers): left alone the compiler took 172-175 for two of them and ran two. The group
+// of lengths 1500-2048 then spills 20 bytes per lane and still makes the 200-image uneven
+// batch about 1 % faster; groups with larger N1 would spill far more and keep the default.
+template <class L0, class... Ls>
+constexpr int kRgmFwdWaves = cmax_n(L0::FN1, Ls::FN1...) <= 40 ? 3 : 1;
+
 template <class L0, class... Ls>
 __global__ void __launch_bounds__(L0::THREADS)
+__attribute__((amdgpu_waves_per_eu(kRgmFwdWaves<L0, Ls...>)))
 k_row_fwd_rgm(const RgBase* basep, const RgRowFwd* tab, const RgItem* items) {
   const RgBase base = *basep;  // written by launch_set_base on this stream
   static_assert(((Ls::THREADS == L0::THREADS) && ...), "one workgroup size per launch");
