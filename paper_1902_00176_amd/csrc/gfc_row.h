@@ -484,14 +484,28 @@ __device__ __forceinline__ void low_lane_factors(cx (&ax0)[kLowBins], cx (&ax1)[
 }
 
 // LDS floats of one slot's plane in the forward row pass: the FFT exchange, or the low-bin
-// lane sums (4 (2K + 1) values at a stride of G + 1 lanes) when larger
+// lane sums (NCV complex values per row, both rows, at a stride of G + 1 lanes) when
+// larger. Where the sums of both rows would outgrow the exchange they pass through the
+// plane one row at a time (kLowRounds = 2), which halves it and holds fewer values live:
+// the 256-point volume slice kernel went from 2 to 3 wavefronts per SIMD (128^3 volumes
+// 0.31 -> 0.30 ms) and the 1024-point row kernel (32 x 32, slots of 32 lanes) from 176
+// registers to 163 and 3 wavefronts (512x512 x 96 0.28 -> 0.27 ms). The 512-point kernel
+// (16 x 32) gained no occupancy and lost 2 % to the extra round, and the uneven batch's
+// groups of 600-1024 points were no faster: those keep one round.
+template <int N1, int N2, int NCV>
+constexpr int kLowRounds =
+    4 * NCV * (RowCfg<N1, N2>::G + 1) > RowCfg<N1, N2>::LDSC &&
+            ((RowCfg<N1, N2>::G == 32 && N1 >= 32) || NCV > 2 * kLowBins + 1)
+        ? 2
+        : 1;
+template <int N1, int N2, int NCV>
+constexpr int kFwdPlaneN = cmax(RowCfg<N1, N2>::LDSC, 4 * NCV * (RowCfg<N1, N2>::G + 1) /
+                                                        kLowRounds<N1, N2, NCV>);
 template <int N1, int N2>
-constexpr int kFwdPlane =
-    cmax(RowCfg<N1, N2>::LDSC, 4 * (2 * kLowBins + 1) * (RowCfg<N1, N2>::G + 1));
+constexpr int kFwdPlane = kFwdPlaneN<N1, N2, 2 * kLowBins + 1>;
 // volume slices also sum Ez: 3K + 2 complex low-bin values per row
 template <int N1, int N2>
-constexpr int kFwdPlane3 =
-    cmax(RowCfg<N1, N2>::LDSC, 4 * (3 * kLowBins + 2) * (RowCfg<N1, N2>::G + 1));
+constexpr int kFwdPlane3 = kFwdPlaneN<N1, N2, 3 * kLowBins + 2>;
 template <int N1, int N2, int SLOTS, int EDIT = kEditNone>
 constexpr int kFwdLds =  // floats per workgroup: one plane per slot
     SLOTS * (EDIT == kIn3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>);
@@ -509,7 +523,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
   constexpr int NV = 4 * NC;             // floats per lane to sum: two rows, re and im
   constexpr int RS = C::G + 1;           // LDS stride of one value over the lanes
   constexpr int PLANE = IS3D ? kFwdPlane3<N1, N2> : kFwdPlane<N1, N2>;
-  static_assert(NV * RS <= PLANE, "the low-bin lane sums fit the slot's plane");
+  constexpr int ROUNDS = kLowRounds<N1, N2, NC>;  // rows of low-bin values per pass
+  static_assert((NV / ROUNDS) * RS <= PLANE, "the low-bin lane sums fit the slot's plane");
   const int slot = SLOTS == 1 ? 0 : int(threadIdx.x) / C::G;  // uniform with one slot
   const int lane = SLOTS == 1 ? int(threadIdx.x) : int(threadIdx.x) % C::G;
   float* pl = lds + slot * PLANE;
@@ -665,31 +680,44 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs p, int bx, int b, 
       }
     }
     // value index: row r of the pair, complex index c < NC (Ex bins 1..K, then Ey bins
-    // 0..K, then for volumes Ez bins 0..K)
+    // 0..K, then for volumes Ez bins 0..K); value v = 2 NC r + 2 c (+1 for the imaginary
+    // part). With two rounds, row 0's values pass through the plane first, then row 1's.
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      constexpr int E2 = 2 * KL + 1;
-      const cx v0 = c < KL ? ax0[c < KL ? c : 0]
-                           : c < E2 ? ay0[c < E2 ? c - KL : 0] : az0[c < E2 ? 0 : c - E2];
-      const cx v1 = c < KL ? ax1[c < KL ? c : 0]
-                           : c < E2 ? ay1[c < E2 ? c - KL : 0] : az1[c < E2 ? 0 : c - E2];
-      pl[(2 * c) * RS + lane] = v0.x;
-      pl[(2 * c + 1) * RS + lane] = v0.y;
-      pl[(2 * NC + 2 * c) * RS + lane] = v1.x;
-      pl[(2 * NC + 2 * c + 1) * RS + lane] = v1.y;
-    }
-    slot_sync();
-    // lane t sums values t, t + G, ... over the N2 lanes that hold elements
+    for (int k = 0; k < NVL; ++k) lowsum[k] = 0.f;
 #pragma unroll
-    for (int k = 0; k < NVL; ++k) {
-      lowsum[k] = 0.f;
-      const int v = lane + C::G * k;
-      if (v < NV) {
+    for (int r = 0; r < ROUNDS; ++r) {
 #pragma unroll
-        for (int j = 0; j < N2; ++j) lowsum[k] += pl[v * RS + j];
+      for (int c = 0; c < NC; ++c) {
+        constexpr int E2 = 2 * KL + 1;
+        const cx v0 = c < KL ? ax0[c < KL ? c : 0]
+                             : c < E2 ? ay0[c < E2 ? c - KL : 0] : az0[c < E2 ? 0 : c - E2];
+        const cx v1 = c < KL ? ax1[c < KL ? c : 0]
+                             : c < E2 ? ay1[c < E2 ? c - KL : 0] : az1[c < E2 ? 0 : c - E2];
+        if (ROUNDS == 1 || r == 0) {
+          pl[(2 * c) * RS + lane] = v0.x;
+          pl[(2 * c + 1) * RS + lane] = v0.y;
+        }
+        if (ROUNDS == 1) {
+          pl[(2 * NC + 2 * c) * RS + lane] = v1.x;
+          pl[(2 * NC + 2 * c + 1) * RS + lane] = v1.y;
+        } else if (r == 1) {
+          pl[(2 * c) * RS + lane] = v1.x;
+          pl[(2 * c + 1) * RS + lane] = v1.y;
+        }
       }
+      slot_sync();
+      // lane t sums values t, t + G, ... (of this round) over the N2 lanes that hold elements
+      constexpr int VR = NV / ROUNDS;
+#pragma unroll
+      for (int k = 0; k < NVL; ++k) {
+        const int v = lane + C::G * k - VR * r;
+        if (v >= 0 && v < VR) {
+#pragma unroll
+          for (int j = 0; j < N2; ++j) lowsum[k] += pl[v * RS + j];
+        }
+      }
+      slot_sync();
     }
-    slot_sync();
     }  // !FULLBINS
 
     cx z[N2];
