@@ -42,16 +42,28 @@ k_zfft(ZfftArgs a) {
   const rsrc_t rT = make_buf(a.T + vol * a.vol_stride, a.vol_stride * 8);
   const rsrc_t rtw = make_buf(a.tw, (long long)P * 8);
 
-  // 1. coalesced load of the column tile: thread -> (plane z, column c)
-  for (int i = t; i < TL * P; i += NT) {
+  // 1. coalesced load of the column tile: thread -> (plane z, column c). All of a thread's
+  // loads are issued before the first is stored to LDS (a loop of load, wait, store paid a
+  // memory latency per plane group).
+  constexpr int NLD = (TL * P + NT - 1) / NT;  // elements per thread
+  f2b v[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = t + k * NT;
     const int c = i % TL, z = i / TL;
     const int l = l0 + c;
-    const bool in = z < a.din && l < a.NH;
+    const bool in = i < TL * P && z < a.din && l < a.NH;
     const long long e =
         (long long)z * a.plane + (a.tiled ? tile_index(y, l, a.R) : y * a.NHP + l);
-    const f2b v = bld2(rT, in ? int(e * 8) : kZOob, 0);
-    s_lds[c][z] = v.x;
-    s_lds[c][C::S + z] = v.y;
+    v[k] = bld2(rT, in ? int(e * 8) : kZOob, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = t + k * NT;
+    if (i < TL * P) {
+      s_lds[i % TL][i / TL] = v[k].x;
+      s_lds[i % TL][C::S + i / TL] = v[k].y;
+    }
   }
   __syncthreads();
 
@@ -95,11 +107,13 @@ k_zfft(ZfftArgs a) {
   }
   __syncthreads();
 
-  // 3. coalesced store of the first dout planes
-  for (int i = t; i < TL * a.dout; i += NT) {
+  // 3. coalesced store of the first dout planes (dout <= P)
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = t + k * NT;
     const int cc = i % TL, z = i / TL;
     const int l = l0 + cc;
-    if (l < a.NH)
+    if (i < TL * a.dout && l < a.NH)
       bst2(rT, s_lds[cc][z], s_lds[cc][C::S + z],
            int(((long long)z * a.plane +
                 (a.tiled ? tile_index(y, l, a.R) : y * a.NHP + l)) * 8), 0);
