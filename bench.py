@@ -305,6 +305,7 @@ def main():
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-color", action="store_true")
     ap.add_argument("--no-edit", action="store_true")
+    ap.add_argument("--no-laplacian", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-small", action="store_true")
@@ -533,6 +534,34 @@ def main():
         edits["params"] = f"threshold at the median gradient magnitude; gdm alpha 0.5, C ~ U[0,1]"
         result["edit"] = edits
         del C
+
+    if not args.no_laplacian:
+        # Algorithm B's own input: the solve from a given Laplacian on the support of div E
+        # (rows of H + 1 by W + 1), its row bins l <= K summed in float64
+        Lap = torch.randn((B, H + 1, W_ + 1), device=dev)
+        Lap -= Lap.mean(dim=(1, 2), keepdim=True)
+
+        def lap_step():
+            st = L.gfc_solve_laplacian(hp, Lap.data_ptr(), u.data_ptr(), B, ws.data_ptr(),
+                                       ws.numel(), sp)
+            if st != 0:
+                raise gfc.GFCError(st, "gfc_solve_laplacian")
+
+        for _ in range(args.warmup):
+            lap_step()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        c0.record(stream)
+        for _ in range(args.steps):
+            lap_step()
+        c1.record(stream)
+        torch.cuda.synchronize()
+        ms_l = c0.elapsed_time(c1) / args.steps
+        result["laplacian"] = {"solves_per_s": B / (ms_l / 1e3), "ms_per_step": ms_l,
+                               "over_plain": ms_l / ms_step,
+                               "input": "L ~ N(0, 1) minus its mean, [B][H+1][W+1]"}
+        del Lap
 
     if not args.no_volume:
         result["volume"] = volume_bench(torch, gfc, dev, stream, max(args.steps // 2, 3))

@@ -13,6 +13,7 @@
 // lane j takes x = j, j + 64, ... and the 64 lane sums are added through LDS.
 #include <hip/hip_runtime.h>
 
+#include "gfc_buf.h"
 #include "gfc_edit.h"
 #include "gfc_internal.h"
 
@@ -165,7 +166,8 @@ namespace gfc {
 namespace {
 
 constexpr int kLapWaves = 4;  // rows per workgroup of k_lap_rows, one per wavefront
-constexpr int kLapBins = 4;   // bins summed per sweep over a row
+constexpr int kLapBins = 5;   // bins summed per sweep over a row (K = 4: one sweep)
+constexpr int kLapChunk = 8;   // elements per lane loaded together in a sweep
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -173,41 +175,55 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// L^[y, l] for l <= K of one row per wavefront: lane j takes x = j, j + 64, ...; the
-// twiddle w_N^(l x) advances by w_N^(64 l) in float64 (at most 64 steps per lane).
+// L^[y, l] for l <= K of one row per wavefront: lane j takes x_k = j + 64 k, and its part
+// is w^(l j) sum_k v_k z^k with z = w^(64 l) (w = w_N, forward sign). The sum over k runs as
+// Goertzel's second-order recurrence in float64, s_k = v_k + 2 Re(z) s_(k-1) - s_(k-2), whose
+// end gives sum_k v_k conj(z)^(n-1-k) = s_(n-1) - z s_(n-2); times z^(n-1) w^(l j), one table
+// entry, that is the lane's part (two operations per element and bin, where rotating the
+// twiddle took ten). The lane's elements are loaded kLapChunk at a time, all in flight
+// together; past x = W they read 0, which the count n of processed elements includes.
 __global__ void __launch_bounds__(64 * kLapWaves) k_lap_rows(LapLowArgs a) {
   const int lane = int(threadIdx.x) & 63;
   const int y = int(blockIdx.x) * kLapWaves + (int(threadIdx.x) >> 6);
   const int b = blockIdx.y;
   if (y > a.H) return;  // no workgroup barrier below
   const float* row = a.L + b * a.img_L + (long long)y * (a.W + 1);
+  const rsrc_t rrow = make_buf(row, (long long)(a.W + 1) * 4);
   double* out = a.Lh + b * a.img_lh + (long long)y * (a.K + 1) * 2;
   for (int l0 = 0; l0 <= a.K; l0 += kLapBins) {
-    double ar[kLapBins], ai[kLapBins], wr[kLapBins], wi[kLapBins], sr[kLapBins], si[kLapBins];
+    double c2[kLapBins], s1[kLapBins], s2[kLapBins];
 #pragma unroll
     for (int i = 0; i < kLapBins; ++i) {
       const int l = l0 + i <= a.K ? l0 + i : 0;
-      const int m = int((long long)l * lane % a.N), d = int((long long)l * 64 % a.N);
-      ar[i] = ai[i] = 0.0;
-      wr[i] = a.twD[2 * m];
-      wi[i] = a.twD[2 * m + 1];
-      sr[i] = a.twD[2 * d];
-      si[i] = a.twD[2 * d + 1];
+      c2[i] = 2.0 * a.twD[2 * int((long long)l * 64 % a.N)];
+      s1[i] = s2[i] = 0.0;
     }
-    for (int x = lane; x <= a.W; x += 64) {
-      const double v = row[x];
+    int n = 0;  // elements processed per lane (the same on every lane)
+    for (int x0 = lane; x0 - lane <= a.W; x0 += 64 * kLapChunk) {
+      float vc[kLapChunk];
 #pragma unroll
-      for (int i = 0; i < kLapBins; ++i) {
-        ar[i] = __builtin_fma(v, wr[i], ar[i]);
-        ai[i] = __builtin_fma(v, wi[i], ai[i]);
-        const double nr = __builtin_fma(wr[i], sr[i], -wi[i] * si[i]);
-        wi[i] = __builtin_fma(wr[i], si[i], wi[i] * sr[i]);
-        wr[i] = nr;
+      for (int k = 0; k < kLapChunk; ++k) vc[k] = bld1(rrow, (x0 + 64 * k) * 4, 0);
+#pragma unroll
+      for (int k = 0; k < kLapChunk; ++k) {
+#pragma unroll
+        for (int i = 0; i < kLapBins; ++i) {
+          const double s0 = __builtin_fma(c2[i], s1[i], double(vc[k]) - s2[i]);
+          s2[i] = s1[i];
+          s1[i] = s0;
+        }
       }
+      n += kLapChunk;
     }
 #pragma unroll
     for (int i = 0; i < kLapBins; ++i) {
-      const double sr_ = wave_sum(ar[i]), si_ = wave_sum(ai[i]);
+      const int l = l0 + i <= a.K ? l0 + i : 0;
+      const int d = int((long long)l * 64 % a.N);
+      const double zr = a.twD[2 * d], zi = a.twD[2 * d + 1];
+      const double qr = __builtin_fma(-zr, s2[i], s1[i]), qi = -zi * s2[i];
+      const int m = int(((long long)l * lane + (long long)l * 64 * (n - 1)) % a.N);
+      const double pr = a.twD[2 * m], pi = a.twD[2 * m + 1];
+      const double ar = __builtin_fma(pr, qr, -pi * qi), ai = __builtin_fma(pr, qi, pi * qr);
+      const double sr_ = wave_sum(ar), si_ = wave_sum(ai);
       if (lane == 0 && l0 + i <= a.K) {
         out[2 * (l0 + i)] = sr_;
         out[2 * (l0 + i) + 1] = si_;
