@@ -136,7 +136,7 @@ def _lengths_from_env():
     return sorted({int(t) for t in v.replace(",", " ").split()})
 
 
-RGM_BUCKET = 12  # row lengths per multi-length ragged launch
+RGM_BUCKET = 24  # row lengths per multi-length ragged launch
 
 
 def rg_buckets(lengths):
