@@ -49,13 +49,17 @@ k_zfft(ZfftArgs a) {
   f2b v[NLD];
 #pragma unroll
   for (int k = 0; k < NLD; ++k) {
-    const int i = t + k * NT;
-    const int c = i % TL, z = i / TL;
-    const int l = l0 + c;
-    const bool in = i < TL * P && z < a.din && l < a.NH;
-    const long long e =
-        (long long)z * a.plane + (a.tiled ? tile_index(y, l, a.R) : y * a.NHP + l);
-    v[k] = bld2(rT, in ? int(e * 8) : kZOob, 0);
+    // element k of every thread lies in planes [k G, k G + G): past din, all read 0
+    v[k] = f2b{0.f, 0.f};
+    if (k * G < a.din) {
+      const int i = t + k * NT;
+      const int c = i % TL, z = i / TL;
+      const int l = l0 + c;
+      const bool in = i < TL * P && z < a.din && l < a.NH;
+      const long long e =
+          (long long)z * a.plane + (a.tiled ? tile_index(y, l, a.R) : y * a.NHP + l);
+      v[k] = bld2(rT, in ? int(e * 8) : kZOob, 0);
+    }
   }
 #pragma unroll
   for (int k = 0; k < NLD; ++k) {
